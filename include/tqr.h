@@ -1,0 +1,176 @@
+/*
+ * tqr -- tiled QR factorization on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library libtqr.so.  The method is the tiled QR factorization
+ * of Bouwmeester's thesis "Tiled Algorithms for Matrix Computations on
+ * Multicore Architectures" (2012), chapter "QR Factorization":
+ *   - A (m x n, n <= m) = Q R, with R = U_l ... U_1 A built from orthogonal
+ *     transformations on tiles (chapter introduction);
+ *   - the matrix is viewed as p x q tiles of nb x nb, p = ceil(m/nb),
+ *     q = ceil(n/nb) (section "The QR factorization algorithm");
+ *   - an elimination list elim(i, piv(i,k), k) fixes which row zeroes which
+ *     tile (algorithm alg.QR, section "Elimination lists"); each elimination
+ *     runs as the six kernels of table tab.kernels (algorithms alg.elimTR and
+ *     alg.elimSQ) and every kernel fires as soon as its inputs are ready
+ *     (section "Execution schemes").
+ *
+ * Conventions shared by every entry point:
+ *   - Matrices are FP64, column-major, in device memory, with a leading
+ *     dimension (lda >= m).  Every numeric entry point is stream-ordered: it
+ *     enqueues work on `stream` and returns without waiting.
+ *   - m and n need not be multiples of nb: the last tile row/column is
+ *     ragged and is treated as if padded with zeros (exact for QR).
+ *   - The caller allocates and owns every buffer.  The library keeps no
+ *     pointer to caller memory beyond the enqueued work.  It caches
+ *     read-only task tables per shape/options in its own device memory.
+ *   - Host-side argument errors return -i for the i-th (1-based) illegal
+ *     argument, or one of the TQR_E_* codes below, and enqueue nothing.
+ *   - Numerical/executor outcomes are reported asynchronously through an
+ *     optional device int32 `info`: 0 ok; j > 0: R(j,j) is exactly zero
+ *     (lstsq only; X is then not defined); TQR_INFO_TIMEOUT: the device
+ *     watchdog stopped the executor; TQR_INFO_NOCONV: refinement did not
+ *     reach its tolerance (X holds the last iterate).
+ *   - NaN/Inf in the input propagate; nothing checks for them.
+ */
+#ifndef TQR_H
+#define TQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Elimination trees (section "Critical paths"): FlatTree = Sameh-Kuck,
+ * BinaryTree, Fibonacci = Modi-Clarke order 1, Greedy (algorithm
+ * alg.tiled-greedy), GrASAP(i) (definition def.grasap, i = opts.param, 0
+ * means 1), PlasmaTree(BS) (BS = opts.param), ASAP on every column.
+ * TQR_AUTO lets the learned selector pick tree and nb (falls back to
+ * GrASAP with nb = 256). */
+enum tqr_tree {
+  TQR_FLAT = 0,
+  TQR_BINARY = 1,
+  TQR_FIBONACCI = 2,
+  TQR_GREEDY = 3,
+  TQR_GRASAP = 4,
+  TQR_PLASMA = 5,
+  TQR_ASAP = 6,
+  TQR_AUTO = 100
+};
+
+/* Kernel families (section "Kernels"): TT triangularises every tile and
+ * kills triangles with TTQRT/TTMQR (algorithm alg.elimTR); HYBRID
+ * triangularises a row at its first use as a pivot and kills a tile that is
+ * still square with TSQRT/TSMQR (algorithm alg.elimSQ), a triangle with
+ * TTQRT/TTMQR.  With FlatTree, HYBRID is the pure TS algorithm. */
+enum tqr_kernels { TQR_TT = 0, TQR_HYBRID = 1 };
+
+/* Arithmetic of the trailing-update kernels (UNMQR/TSMQR/TTMQR). */
+enum tqr_dtype { TQR_F64 = 0, TQR_F32 = 1, TQR_BF16 = 2 };
+
+/* How the task graph is run: one persistent kernel with a device ready
+ * queue (default), or one launch per task in list order (reference). */
+enum tqr_exec { TQR_EXEC_PERSISTENT = 0, TQR_EXEC_SEQUENTIAL = 1 };
+
+typedef struct tqr_opts {
+  int32_t nb;           /* tile size: 32, 64, 128 or 256 (default 256)      */
+  int32_t ib;           /* inner block: 16 or 32, divides nb (default 32)   */
+  int32_t tree;         /* enum tqr_tree (default TQR_GRASAP)               */
+  int32_t kernels;      /* enum tqr_kernels (default TQR_TT)                */
+  int32_t param;        /* PlasmaTree BS / GrASAP i (default 0)             */
+  int32_t update_dtype; /* enum tqr_dtype (default TQR_F64)                 */
+  int32_t exec;         /* enum tqr_exec (default persistent)               */
+  int32_t stripes;      /* update tasks per tile (0 = library default)      */
+  int32_t max_refine;   /* refinement steps for mixed precision (def. 10)   */
+  int32_t priority;     /* 1 = critical-path-first ready order (default 1)  */
+  double refine_tol;    /* refinement stop, relative backward error (0=auto)*/
+} tqr_opts;
+
+enum {
+  TQR_OK = 0,
+  TQR_E_HIP = -100,         /* a HIP call failed while enqueueing          */
+  TQR_E_WORKSPACE = -101,   /* workspace smaller than tqr_workspace_size   */
+  TQR_E_UNSUPPORTED = -102, /* option combination not built                */
+  TQR_E_NOMEM = -103,       /* library could not allocate its task tables  */
+  TQR_E_INTERNAL = -104     /* task graph failed its host-side validation  */
+};
+enum { TQR_INFO_TIMEOUT = -1000, TQR_INFO_NOCONV = -1001 };
+
+/* Fills *o with the defaults listed in tqr_opts. */
+void tqr_default_opts(tqr_opts *o);
+
+/* Bytes of device workspace needed by tqr_factor / tqr_factor_ex /
+ * tqr_apply_qt (with up to nrhs right-hand sides) for an m x n matrix:
+ * the T factors of every factor kernel (two ib x nb blocks per tile, one
+ * for GEQRT and one for the kernel that zeroes the tile) plus executor
+ * state.  o = NULL means defaults.  Returns 0 for invalid arguments. */
+size_t tqr_workspace_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o);
+
+/* Factor A = Q R in place with tile size nb and elimination tree `tree`
+ * (other options default; lda = m).  On return (stream-ordered) the upper
+ * triangle of the first n rows of A holds R; the other entries and the
+ * workspace T hold the Householder vectors and T factors that
+ * tqr_apply_qt uses.  T must be tqr_workspace_size(m, n, 0, opts) bytes
+ * with opts.nb = nb, opts.tree = tree. */
+int tqr_factor(int64_t m, int64_t n, int32_t nb, int32_t tree, double *A, void *T,
+               hipStream_t stream);
+
+/* As tqr_factor with explicit lda, workspace size and options.  info: NULL
+ * or a device int32 that receives 0 or TQR_INFO_TIMEOUT. */
+int tqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, void *T, size_t t_bytes,
+                  const tqr_opts *o, int32_t *info, hipStream_t stream);
+
+/* B <- Q^T B for the factorization held in (A, T) by a previous factor call
+ * with the same m, n and options (the thesis's update kernels UNMQR, TTMQR,
+ * TSMQR replayed in list order on the columns of B).  B is m x nrhs,
+ * column-major, ldb >= m.  T's factor part is read; its executor part is
+ * reused as scratch, so calls on one T must not overlap. */
+int tqr_apply_qt(int64_t m, int64_t n, const double *A, int64_t lda, void *T, size_t t_bytes,
+                 int64_t nrhs, double *B, int64_t ldb, const tqr_opts *o, int32_t *info,
+                 hipStream_t stream);
+
+/* Least squares min ||A x - b||_2 for each of nrhs right-hand sides
+ * (chapter introduction: QR solves the m-equation, n-unknown least-squares
+ * problem): X = R^{-1} (Q^T B)(1:n, :).  A (m x n, lda) and B (m x nrhs,
+ * ldb) are not modified; X is n x nrhs (ldx >= n).  work must be
+ * tqr_lstsq_work_size bytes.  With opts.update_dtype != TQR_F64 the
+ * factorization uses low-precision updates and X is refined in FP64
+ * against the caller's A (at most opts.max_refine steps); info then
+ * reports TQR_INFO_NOCONV if the tolerance was not reached. */
+size_t tqr_lstsq_work_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o);
+int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+              int64_t ldb, double *X, int64_t ldx, void *work, size_t work_bytes,
+              const tqr_opts *o, int32_t *info, hipStream_t stream);
+
+/* ----------------------------------------------- host-only list services */
+
+/* Elimination list of `tree` (param: PlasmaTree BS / GrASAP i) for p x q
+ * tiles (1 <= q <= p), as 1-based (i, piv, k) triples in list order.
+ * Returns the list length, writing the triples only if cap >= length;
+ * negative on bad arguments.  No GPU is touched. */
+int64_t tqr_tree_list(int32_t tree, int32_t p, int32_t q, int32_t param, int32_t *i_out,
+                      int32_t *piv_out, int32_t *k_out, int64_t cap);
+
+/* Critical path, in units of nb^3/3 (table tab.kernels weights), of the
+ * tiled algorithm given by the list and kernel family, on unbounded
+ * processors; computed as the longest path of the task graph the executor
+ * runs.  zero_t (p*q, row-major, may be NULL) receives the end time of the
+ * kernel that zeroes each tile; counts (6, may be NULL) receives the number
+ * of GEQRT, TSQRT, TTQRT, UNMQR, TSMQR, TTMQR tasks.  No GPU is touched. */
+int64_t tqr_tree_cp(int32_t tree, int32_t p, int32_t q, int32_t param, int32_t kernels,
+                    int64_t *zero_t, int64_t *counts);
+
+/* Number of tasks and dependency edges of the executor's graph for the
+ * given problem (factor only).  No GPU is touched. */
+int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, int64_t *nedges);
+
+const char *tqr_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TQR_H */

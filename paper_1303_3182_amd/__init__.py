@@ -1,0 +1,16 @@
+"""tqr: tiled QR factorization on one AMD Instinct MI355X.
+
+Thin Python binding of libtqr.so (the C ABI in include/tqr.h).  Every step
+of the factorization, Q^T application and least-squares solve runs in the
+library's HIP kernels; this module only marshals arguments.  PyTorch
+supplies device memory and the current stream.
+
+Matrices are float64 column-major device tensors (stride (1, ld)).
+"""
+from ._binding import (  # noqa: F401
+    ASAP, BF16, BINARY, EXEC_PERSISTENT, EXEC_SEQUENTIAL, F32, F64, FIBONACCI, FLAT,
+    GRASAP, GREEDY, HYBRID, PLASMA, TREES, TT, AUTO, Opts, TqrError, default_opts, lib,
+    library_path, tqr_apply_qt, tqr_factor, tqr_factor_ex, tqr_graph_stats, tqr_lstsq,
+    tqr_lstsq_work_size, tqr_tree_cp, tqr_tree_list, tqr_workspace_size,
+)
+from .api import apply_qt, colmajor, factor, lstsq, workspace  # noqa: F401

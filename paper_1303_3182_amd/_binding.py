@@ -1,0 +1,154 @@
+"""ctypes view of libtqr.so: one Python function per C entry point, same
+names and argument order as include/tqr.h (argument marshalling only)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libtqr.so")
+
+FLAT, BINARY, FIBONACCI, GREEDY, GRASAP, PLASMA, ASAP, AUTO = 0, 1, 2, 3, 4, 5, 6, 100
+TREES = {"flat": FLAT, "binary": BINARY, "fibonacci": FIBONACCI, "greedy": GREEDY,
+         "grasap": GRASAP, "plasma": PLASMA, "asap": ASAP, "auto": AUTO}
+TT, HYBRID = 0, 1
+F64, F32, BF16 = 0, 1, 2
+EXEC_PERSISTENT, EXEC_SEQUENTIAL = 0, 1
+
+
+class TqrError(RuntimeError):
+    pass
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int32), ("ib", ctypes.c_int32), ("tree", ctypes.c_int32),
+                ("kernels", ctypes.c_int32), ("param", ctypes.c_int32),
+                ("update_dtype", ctypes.c_int32), ("exec", ctypes.c_int32),
+                ("stripes", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+                ("priority", ctypes.c_int32), ("refine_tol", ctypes.c_double)]
+
+
+_lib = None
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def lib():
+    """The loaded libtqr.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise TqrError("libtqr.so is not built (run __graft_entry__.build() or "
+                           "python -m paper_1303_3182_amd.build)")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        op = ctypes.POINTER(Opts)
+        i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+        sig = {
+            "tqr_default_opts": (None, [op]),
+            "tqr_workspace_size": (sz, [i64, i64, i64, op]),
+            "tqr_factor": (ctypes.c_int, [i64, i64, i32, i32, vp, vp, vp]),
+            "tqr_factor_ex": (ctypes.c_int, [i64, i64, vp, i64, vp, sz, op, vp, vp]),
+            "tqr_apply_qt": (ctypes.c_int, [i64, i64, vp, i64, vp, sz, i64, vp, i64, op, vp, vp]),
+            "tqr_lstsq_work_size": (sz, [i64, i64, i64, op]),
+            "tqr_lstsq": (ctypes.c_int, [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, op, vp, vp]),
+            "tqr_tree_list": (i64, [i32, i32, i32, i32, i32p, i32p, i32p, i64]),
+            "tqr_tree_cp": (i64, [i32, i32, i32, i32, i32, i64p, i64p]),
+            "tqr_graph_stats": (ctypes.c_int, [i64, i64, op, i64p, i64p]),
+            "tqr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        msg = lib().tqr_strerror(rc).decode()
+        raise TqrError("%s failed: %d (%s)" % (what, rc, msg))
+    return rc
+
+
+def _opts_ptr(o):
+    return None if o is None else ctypes.byref(o)
+
+
+def default_opts(**kw):
+    o = Opts()
+    lib().tqr_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "tree" and isinstance(v, str):
+            v = TREES[v]
+        if k == "kernels" and isinstance(v, str):
+            v = {"tt": TT, "hybrid": HYBRID, "ts": HYBRID}[v]
+        if k == "update_dtype" and isinstance(v, str):
+            v = {"f64": F64, "f32": F32, "bf16": BF16}[v]
+        setattr(o, k, v)
+    return o
+
+
+def tqr_workspace_size(m, n, nrhs=0, opts=None):
+    return int(lib().tqr_workspace_size(m, n, nrhs, _opts_ptr(opts)))
+
+
+def tqr_factor(m, n, nb, tree, A, T, stream):
+    return _check(lib().tqr_factor(m, n, nb, tree, A, T, stream), "tqr_factor")
+
+
+def tqr_factor_ex(m, n, A, lda, T, t_bytes, opts, info, stream):
+    return _check(lib().tqr_factor_ex(m, n, A, lda, T, t_bytes, _opts_ptr(opts), info, stream),
+                  "tqr_factor_ex")
+
+
+def tqr_apply_qt(m, n, A, lda, T, t_bytes, nrhs, B, ldb, opts, info, stream):
+    return _check(lib().tqr_apply_qt(m, n, A, lda, T, t_bytes, nrhs, B, ldb, _opts_ptr(opts), info,
+                                     stream), "tqr_apply_qt")
+
+
+def tqr_lstsq_work_size(m, n, nrhs, opts=None):
+    return int(lib().tqr_lstsq_work_size(m, n, nrhs, _opts_ptr(opts)))
+
+
+def tqr_lstsq(m, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, opts, info, stream):
+    return _check(lib().tqr_lstsq(m, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes,
+                                  _opts_ptr(opts), info, stream), "tqr_lstsq")
+
+
+def tqr_tree_list(tree, p, q, param=0):
+    """1-based (i, piv, k) triples of the elimination list (host only)."""
+    if isinstance(tree, str):
+        tree = TREES[tree]
+    L = lib()
+    n = L.tqr_tree_list(tree, p, q, param, None, None, None, 0)
+    if n < 0:
+        raise TqrError("tqr_tree_list: bad arguments (%d)" % n)
+    a = (ctypes.c_int32 * max(n, 1))()
+    b = (ctypes.c_int32 * max(n, 1))()
+    c = (ctypes.c_int32 * max(n, 1))()
+    L.tqr_tree_list(tree, p, q, param, a, b, c, n)
+    return [(a[e], b[e], c[e]) for e in range(n)]
+
+
+def tqr_tree_cp(tree, p, q, param=0, kernels=TT, want_zero=False):
+    """Critical path (units nb^3/3); optionally (cp, zero_times p x q, counts)."""
+    if isinstance(tree, str):
+        tree = TREES[tree]
+    zt = (ctypes.c_int64 * (p * q))()
+    cnt = (ctypes.c_int64 * 6)()
+    cp = lib().tqr_tree_cp(tree, p, q, param, kernels, zt, cnt)
+    if cp < 0:
+        raise TqrError("tqr_tree_cp: bad arguments (%d)" % cp)
+    if not want_zero:
+        return int(cp)
+    rows = [[zt[i * q + k] for k in range(q)] for i in range(p)]
+    return int(cp), rows, list(cnt)
+
+
+def tqr_graph_stats(m, n, opts=None):
+    nt, ne = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().tqr_graph_stats(m, n, _opts_ptr(opts), ctypes.byref(nt), ctypes.byref(ne)),
+           "tqr_graph_stats")
+    return nt.value, ne.value

@@ -1,0 +1,76 @@
+"""Tensor-level helpers over the C ABI (allocation and pointer marshalling
+only; all arithmetic runs in libtqr.so)."""
+import torch
+
+from . import _binding as B
+
+
+def _ptr(t):
+    return None if t is None else ctypes_ptr(t)
+
+
+def ctypes_ptr(t):
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def colmajor(x, device="cuda"):
+    """A column-major float64 device copy of a 2-D array/tensor (stride (1, m))."""
+    t = torch.as_tensor(x, dtype=torch.float64)
+    if t.dim() == 1:
+        t = t[:, None]
+    m, n = t.shape
+    out = torch.empty((n, m), dtype=torch.float64, device=device).t()
+    out.copy_(t)
+    return out
+
+
+def _ld(t):
+    if t.dim() != 2 or t.stride(0) != 1 or t.dtype != torch.float64 or not t.is_cuda:
+        raise B.TqrError("expected a column-major float64 CUDA tensor")
+    return max(t.stride(1), t.shape[0])
+
+
+def workspace(m, n, nrhs=0, opts=None, device="cuda"):
+    nbytes = B.tqr_workspace_size(m, n, nrhs, opts)
+    if nbytes == 0:
+        raise B.TqrError("invalid shape/options for workspace")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def factor(A, opts=None, T=None, info=None, nrhs=0):
+    """Factor the column-major tensor A in place; returns (A, T).  The
+    workspace T is sized for a later apply_qt with up to nrhs columns."""
+    m, n = A.shape
+    if T is None:
+        T = workspace(m, n, nrhs, opts, A.device)
+    B.tqr_factor_ex(m, n, A.data_ptr(), _ld(A), T.data_ptr(), T.numel(), opts,
+                    None if info is None else info.data_ptr(), _stream())
+    return A, T
+
+
+def apply_qt(A, T, Bm, opts=None, info=None):
+    """B <- Q^T B for a factorization produced by factor() with the same opts."""
+    m, n = A.shape
+    B.tqr_apply_qt(m, n, A.data_ptr(), _ld(A), T.data_ptr(), T.numel(), Bm.shape[1], Bm.data_ptr(),
+                   _ld(Bm), opts, None if info is None else info.data_ptr(), _stream())
+    return Bm
+
+
+def lstsq(A, Bm, opts=None, X=None, work=None, info=None):
+    """Least-squares solution X (n x nrhs) of min ||A X - B||; A, B untouched."""
+    m, n = A.shape
+    nrhs = Bm.shape[1]
+    if X is None:
+        X = torch.empty((nrhs, n), dtype=torch.float64, device=A.device).t()
+    if work is None:
+        nbytes = B.tqr_lstsq_work_size(m, n, nrhs, opts)
+        if nbytes == 0:
+            raise B.TqrError("invalid shape/options for lstsq")
+        work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    B.tqr_lstsq(m, n, nrhs, A.data_ptr(), _ld(A), Bm.data_ptr(), _ld(Bm), X.data_ptr(), _ld(X),
+                work.data_ptr(), work.numel(), opts, None if info is None else info.data_ptr(), _stream())
+    return X

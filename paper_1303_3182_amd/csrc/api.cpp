@@ -1,0 +1,448 @@
+// C ABI of libtqr.so (declared in include/tqr.h): argument checks, the
+// per-shape plan cache (task graphs uploaded once per device), workspace
+// layout and launches of the device executor.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "graph.h"
+#include "tqr.h"
+#include "tqr_types.h"
+
+namespace tqr {
+hipError_t launch_exec(const ExecArgs &a, int mode, int grid, const int32_t *order, int32_t *info,
+                       hipStream_t s);
+int exec_occupancy(int nb, int ib);
+bool config_supported(int nb, int ib);
+int chunk_width(int nb, int ib);
+}  // namespace tqr
+
+using namespace tqr;
+
+namespace {
+
+constexpr size_t kHeader = 256;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+enum PlanKind { PK_FACTOR = 0, PK_APPLY = 1, PK_SOLVE = 2 };
+
+struct PlanKey {
+  int kind, p, q, nbcols, family, tree, param, stripes, stripes_b, priority;
+  bool operator<(const PlanKey &o) const {
+    return std::tie(kind, p, q, nbcols, family, tree, param, stripes, stripes_b, priority) <
+           std::tie(o.kind, o.p, o.q, o.nbcols, o.family, o.tree, o.param, o.stripes, o.stripes_b,
+                    o.priority);
+  }
+};
+
+struct HostPlan {
+  Graph g;
+  bool valid = false;
+};
+
+struct DevicePlan {
+  Task *tasks = nullptr;
+  int32_t *succ_off = nullptr, *succ = nullptr, *indeg0 = nullptr, *ready0 = nullptr;
+  int32_t ntasks = 0, nready0 = 0;
+};
+
+std::mutex g_mu;
+std::map<PlanKey, std::shared_ptr<HostPlan>> g_host;
+std::map<std::pair<int, PlanKey>, DevicePlan> g_dev;
+std::map<int, int> g_grid;
+std::map<std::pair<int, int>, int64_t> g_spin;
+
+std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_host.find(k);
+    if (it != g_host.end()) return it->second;
+  }
+  auto hp = std::make_shared<HostPlan>();
+  GraphSpec spec;
+  spec.p = k.p;
+  spec.q = k.q;
+  spec.family = k.family;
+  spec.stripes = k.stripes;
+  spec.nbcols = k.nbcols;
+  spec.stripes_b = k.stripes_b;
+  spec.panels = (k.kind == PK_FACTOR);
+  spec.b_updates = (k.kind == PK_APPLY);
+  spec.solve = (k.kind == PK_SOLVE);
+  std::vector<Elim> list;
+  if (k.kind != PK_SOLVE) list = make_list(k.tree, k.p, k.q, k.param);
+  hp->g = build_graph(list, spec);
+  finalize(hp->g, k.priority != 0);
+  hp->valid = validate(hp->g);
+  // the host structure is only needed for sequential order and statistics
+  hp->g.preds.clear();
+  hp->g.preds.shrink_to_fit();
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_host.find(k);
+  if (it != g_host.end()) return it->second;
+  g_host[k] = hp;
+  return hp;
+}
+
+template <typename T>
+hipError_t upload(T **dst, const std::vector<T> &src) {
+  size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), bytes);
+  if (e != hipSuccess) return e;
+  if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+int device_plan(const PlanKey &k, const HostPlan &hp, int dev, DevicePlan *out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, k);
+  auto it = g_dev.find(key);
+  if (it != g_dev.end()) {
+    *out = it->second;
+    return TQR_OK;
+  }
+  DevicePlan d;
+  const Graph &g = hp.g;
+  if (upload(&d.tasks, g.tasks) != hipSuccess || upload(&d.succ_off, g.succ_off) != hipSuccess ||
+      upload(&d.succ, g.succ) != hipSuccess || upload(&d.indeg0, g.indeg0) != hipSuccess ||
+      upload(&d.ready0, g.ready0) != hipSuccess)
+    return TQR_E_NOMEM;
+  d.ntasks = (int32_t)g.tasks.size();
+  d.nready0 = (int32_t)g.ready0.size();
+  g_dev[key] = d;
+  *out = d;
+  return TQR_OK;
+}
+
+int grid_size(int dev, int nb, int ib) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_grid.find(dev * 1024 + nb * 4 + ib / 16);
+  if (it != g_grid.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 1;
+  const int occ = exec_occupancy(nb, ib);
+  const int grid = cus * std::max(1, occ);
+  g_grid[dev * 1024 + nb * 4 + ib / 16] = grid;
+  return grid;
+}
+
+int64_t spin_limit_ticks(int dev) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_spin.find({dev, 0});
+  if (it != g_spin.end()) return it->second;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    khz = 100000;
+  const int64_t ticks = (int64_t)khz * 1000 * 30;  // 30 s without progress on one slot
+  g_spin[{dev, 0}] = ticks;
+  return ticks;
+}
+
+struct Resolved {
+  int nb, ib, tree, param, family, stripes, priority, exec;
+};
+
+int resolve(const tqr_opts *o, Resolved *r) {
+  tqr_opts d;
+  tqr_default_opts(&d);
+  const tqr_opts &x = o ? *o : d;
+  r->nb = x.nb;
+  r->ib = x.ib;
+  r->tree = x.tree;
+  r->param = x.param;
+  r->family = x.kernels;
+  r->priority = x.priority;
+  r->exec = x.exec;
+  if (r->tree == TQR_AUTO) {
+    r->tree = TQR_GRASAP;
+    r->param = 1;
+  }
+  if (!config_supported(r->nb, r->ib)) return TQR_E_UNSUPPORTED;
+  if (r->tree < TQR_FLAT || r->tree > TQR_ASAP) return TQR_E_UNSUPPORTED;
+  if (r->family != TQR_TT && r->family != TQR_HYBRID) return TQR_E_UNSUPPORTED;
+  if (r->exec != TQR_EXEC_PERSISTENT && r->exec != TQR_EXEC_SEQUENTIAL) return TQR_E_UNSUPPORTED;
+  if (x.update_dtype != TQR_F64) return TQR_E_UNSUPPORTED;
+  const int wc = chunk_width(r->nb, r->ib);
+  int s = x.stripes;
+  if (s <= 0) s = std::max(1, r->nb / std::max(wc, 64));
+  if (s > r->nb / wc) s = r->nb / wc;
+  while ((r->nb / wc) % s) s--;  // stripe width is a multiple of the chunk width
+  r->stripes = std::max(1, s);
+  return TQR_OK;
+}
+
+PlanKey make_key(int kind, int p, int q, int nbcols, const Resolved &r) {
+  PlanKey k{};
+  k.kind = kind;
+  k.p = p;
+  k.q = q;
+  k.nbcols = nbcols;
+  k.family = r.family;
+  k.tree = (kind == PK_SOLVE) ? 0 : r.tree;
+  k.param = (kind == PK_SOLVE) ? 0 : r.param;
+  k.stripes = r.stripes;
+  k.stripes_b = (kind == PK_FACTOR) ? 1 : r.stripes;
+  k.priority = r.priority;
+  if (kind == PK_SOLVE) k.family = 0;
+  return k;
+}
+
+size_t tfactor_bytes(int64_t p, int64_t q, int nb, int ib) {
+  return (size_t)p * q * 2 * ib * nb * sizeof(double);
+}
+
+size_t state_bytes(int64_t ntasks) {
+  return align_up(sizeof(ExecCtl)) + 2 * align_up((size_t)std::max<int64_t>(ntasks, 1) * 4);
+}
+
+// Runs one plan on the device.
+int run_plan(int kind, int64_t m, int64_t n, double *A, int64_t lda, double *B, int64_t ldb,
+             int64_t nrhs, void *T, size_t t_bytes, const Resolved &r, int32_t *info,
+             hipStream_t stream) {
+  const int nb = r.nb;
+  const int64_t p = cdiv(m, nb), q = cdiv(n, nb);
+  const int nbcols = (kind == PK_FACTOR) ? 0 : (int)cdiv(nrhs, nb);
+  const PlanKey key = make_key(kind, (int)p, (int)q, nbcols, r);
+  auto hp = host_plan(key);
+  if (!hp->valid) return TQR_E_INTERNAL;
+  const size_t tf = tfactor_bytes(p, q, nb, r.ib);
+  const size_t need = kHeader + align_up(tf) + state_bytes((int64_t)hp->g.tasks.size());
+  if (t_bytes < need) return TQR_E_WORKSPACE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TQR_E_HIP;
+  DevicePlan dp;
+  int rc = device_plan(key, *hp, dev, &dp);
+  if (rc) return rc;
+  char *base = static_cast<char *>(T);
+  ExecArgs a{};
+  a.tasks = dp.tasks;
+  a.succ_off = dp.succ_off;
+  a.succ = dp.succ;
+  a.indeg0 = dp.indeg0;
+  a.ready0 = dp.ready0;
+  a.ntasks = dp.ntasks;
+  a.nready0 = dp.nready0;
+  char *st = base + kHeader + align_up(tf);
+  a.ctl = reinterpret_cast<ExecCtl *>(st);
+  a.queue = reinterpret_cast<int32_t *>(st + align_up(sizeof(ExecCtl)));
+  a.indeg = reinterpret_cast<int32_t *>(st + align_up(sizeof(ExecCtl)) +
+                                        align_up((size_t)std::max<int32_t>(a.ntasks, 1) * 4));
+  a.A = A;
+  a.lda = lda;
+  a.m = m;
+  a.n = n;
+  a.B = B;
+  a.ldb = ldb;
+  a.nrhs = nrhs;
+  a.Tf = reinterpret_cast<double *>(base + kHeader);
+  a.p = (int)p;
+  a.q = (int)q;
+  a.nb = nb;
+  a.ib = r.ib;
+  a.sw = nb / (kind == PK_FACTOR ? key.stripes : key.stripes_b);
+  a.spin_limit = spin_limit_ticks(dev);
+  const int grid = grid_size(dev, nb, r.ib);
+  hipError_t e = launch_exec(a, r.exec == TQR_EXEC_SEQUENTIAL ? 1 : 0, grid, hp->g.order.data(),
+                             info, stream);
+  return e == hipSuccess ? TQR_OK : TQR_E_HIP;
+}
+
+int64_t plan_tasks(int kind, int64_t m, int64_t n, int64_t nrhs, const Resolved &r) {
+  const int64_t p = cdiv(m, r.nb), q = cdiv(n, r.nb);
+  const int nbcols = (kind == PK_FACTOR) ? 0 : (int)cdiv(nrhs, r.nb);
+  return (int64_t)host_plan(make_key(kind, (int)p, (int)q, nbcols, r))->g.tasks.size();
+}
+
+}  // namespace
+
+extern "C" {
+
+void tqr_default_opts(tqr_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->nb = 256;
+  o->ib = 32;
+  o->tree = TQR_GRASAP;
+  o->kernels = TQR_TT;
+  o->param = 0;
+  o->update_dtype = TQR_F64;
+  o->exec = TQR_EXEC_PERSISTENT;
+  o->stripes = 0;
+  o->max_refine = 10;
+  o->priority = 1;
+  o->refine_tol = 0.0;
+}
+
+size_t tqr_workspace_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o) {
+  if (m < 1 || n < 1 || n > m || nrhs < 0) return 0;
+  Resolved r;
+  if (resolve(o, &r)) return 0;
+  const int64_t p = cdiv(m, r.nb), q = cdiv(n, r.nb);
+  int64_t nt = plan_tasks(PK_FACTOR, m, n, 0, r);
+  if (nrhs > 0) nt = std::max(nt, plan_tasks(PK_APPLY, m, n, nrhs, r));
+  return kHeader + align_up(tfactor_bytes(p, q, r.nb, r.ib)) + state_bytes(nt);
+}
+
+int tqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, void *T, size_t t_bytes,
+                  const tqr_opts *o, int32_t *info, hipStream_t stream) {
+  if (m < 1) return -1;
+  if (n < 1 || n > m) return -2;
+  if (!A) return -3;
+  if (lda < m) return -4;
+  if (!T) return -5;
+  Resolved r;
+  int rc = resolve(o, &r);
+  if (rc) return rc;
+  return run_plan(PK_FACTOR, m, n, A, lda, nullptr, 0, 0, T, t_bytes, r, info, stream);
+}
+
+int tqr_factor(int64_t m, int64_t n, int32_t nb, int32_t tree, double *A, void *T, hipStream_t stream) {
+  tqr_opts o;
+  tqr_default_opts(&o);
+  o.nb = nb;
+  o.tree = tree;
+  const size_t need = tqr_workspace_size(m, n, 0, &o);
+  if (need == 0) return (m < 1) ? -1 : ((n < 1 || n > m) ? -2 : TQR_E_UNSUPPORTED);
+  return tqr_factor_ex(m, n, A, m, T, need, &o, nullptr, stream);
+}
+
+int tqr_apply_qt(int64_t m, int64_t n, const double *A, int64_t lda, void *T, size_t t_bytes,
+                 int64_t nrhs, double *B, int64_t ldb, const tqr_opts *o, int32_t *info,
+                 hipStream_t stream) {
+  if (m < 1) return -1;
+  if (n < 1 || n > m) return -2;
+  if (!A) return -3;
+  if (lda < m) return -4;
+  if (!T) return -5;
+  if (nrhs < 0) return -7;
+  if (!B && nrhs > 0) return -8;
+  if (ldb < m) return -9;
+  if (nrhs == 0) return TQR_OK;
+  Resolved r;
+  int rc = resolve(o, &r);
+  if (rc) return rc;
+  return run_plan(PK_APPLY, m, n, const_cast<double *>(A), lda, B, ldb, nrhs, T, t_bytes, r, info,
+                  stream);
+}
+
+size_t tqr_lstsq_work_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o) {
+  if (m < 1 || n < 1 || n > m || nrhs < 1) return 0;
+  Resolved r;
+  if (resolve(o, &r)) return 0;
+  size_t t = tqr_workspace_size(m, n, nrhs, o);
+  const int64_t nt = plan_tasks(PK_SOLVE, m, n, nrhs, r);
+  t = std::max(t, kHeader + align_up(tfactor_bytes(cdiv(m, r.nb), cdiv(n, r.nb), r.nb, r.ib)) +
+                      state_bytes(nt));
+  return align_up((size_t)m * n * 8) + align_up((size_t)m * nrhs * 8) + t;
+}
+
+int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+              int64_t ldb, double *X, int64_t ldx, void *work, size_t work_bytes, const tqr_opts *o,
+              int32_t *info, hipStream_t stream) {
+  if (m < 1) return -1;
+  if (n < 1 || n > m) return -2;
+  if (nrhs < 1) return -3;
+  if (!A) return -4;
+  if (lda < m) return -5;
+  if (!B) return -6;
+  if (ldb < m) return -7;
+  if (!X) return -8;
+  if (ldx < n) return -9;
+  if (!work) return -10;
+  Resolved r;
+  int rc = resolve(o, &r);
+  if (rc) return rc;
+  const size_t need = tqr_lstsq_work_size(m, n, nrhs, o);
+  if (work_bytes < need) return TQR_E_WORKSPACE;
+  char *w = static_cast<char *>(work);
+  double *Ac = reinterpret_cast<double *>(w);
+  double *Bc = reinterpret_cast<double *>(w + align_up((size_t)m * n * 8));
+  char *T = w + align_up((size_t)m * n * 8) + align_up((size_t)m * nrhs * 8);
+  const size_t tb = work_bytes - (size_t)(T - w);
+  if (hipMemcpy2DAsync(Ac, m * 8, A, lda * 8, m * 8, n, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+    return TQR_E_HIP;
+  if (hipMemcpy2DAsync(Bc, m * 8, B, ldb * 8, m * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+    return TQR_E_HIP;
+  rc = run_plan(PK_FACTOR, m, n, Ac, m, nullptr, 0, 0, T, tb, r, info, stream);
+  if (rc) return rc;
+  rc = run_plan(PK_APPLY, m, n, Ac, m, Bc, m, nrhs, T, tb, r, info, stream);
+  if (rc) return rc;
+  rc = run_plan(PK_SOLVE, m, n, Ac, m, Bc, m, nrhs, T, tb, r, info, stream);
+  if (rc) return rc;
+  if (hipMemcpy2DAsync(X, ldx * 8, Bc, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+    return TQR_E_HIP;
+  return TQR_OK;
+}
+
+int64_t tqr_tree_list(int32_t tree, int32_t p, int32_t q, int32_t param, int32_t *i_out,
+                      int32_t *piv_out, int32_t *k_out, int64_t cap) {
+  if (p < 1 || q < 1 || q > p) return -2;
+  if (tree < TQR_FLAT || tree > TQR_ASAP) return -1;
+  std::vector<Elim> l = make_list(tree, p, q, param);
+  if ((int64_t)l.size() <= cap && i_out && piv_out && k_out)
+    for (size_t e = 0; e < l.size(); e++) {
+      i_out[e] = l[e].i + 1;
+      piv_out[e] = l[e].piv + 1;
+      k_out[e] = l[e].k + 1;
+    }
+  return (int64_t)l.size();
+}
+
+int64_t tqr_tree_cp(int32_t tree, int32_t p, int32_t q, int32_t param, int32_t kernels,
+                    int64_t *zero_t, int64_t *counts) {
+  if (p < 1 || q < 1 || q > p) return -2;
+  if (tree < TQR_FLAT || tree > TQR_ASAP) return -1;
+  if (kernels != TQR_TT && kernels != TQR_HYBRID) return -5;
+  std::vector<Elim> l = make_list(tree, p, q, param);
+  GraphSpec spec;
+  spec.p = p;
+  spec.q = q;
+  spec.family = kernels;
+  std::vector<double> zt;
+  Graph g = build_graph(l, spec, &zt, nullptr);
+  if (zero_t)
+    for (size_t x = 0; x < zt.size(); x++) zero_t[x] = (int64_t)zt[x];
+  if (counts) {
+    for (int c = 0; c < 6; c++) counts[c] = 0;
+    for (const Task &t : g.tasks)
+      if (t.kind < 6) counts[t.kind]++;
+  }
+  return (int64_t)g.cp;
+}
+
+int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, int64_t *nedges) {
+  if (m < 1 || n < 1 || n > m) return -1;
+  Resolved r;
+  int rc = resolve(o, &r);
+  if (rc) return rc;
+  auto hp = host_plan(make_key(PK_FACTOR, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), 0, r));
+  if (ntasks) *ntasks = (int64_t)hp->g.tasks.size();
+  if (nedges) *nedges = hp->g.nedges;
+  return hp->valid ? TQR_OK : TQR_E_INTERNAL;
+}
+
+const char *tqr_strerror(int code) {
+  switch (code) {
+    case TQR_OK: return "ok";
+    case TQR_E_HIP: return "a HIP call failed";
+    case TQR_E_WORKSPACE: return "workspace too small";
+    case TQR_E_UNSUPPORTED: return "unsupported option combination";
+    case TQR_E_NOMEM: return "out of device memory for task tables";
+    case TQR_E_INTERNAL: return "task graph failed validation";
+    case TQR_INFO_TIMEOUT: return "device executor watchdog fired";
+    case TQR_INFO_NOCONV: return "refinement did not converge";
+    default: return code < 0 ? "illegal argument" : "R has an exactly zero diagonal entry";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,427 @@
+// Elimination lists (thesis section "Critical paths") and the task graph of
+// the tiled algorithm (sections "Kernels", "Execution schemes").
+#include "graph.h"
+
+#include <algorithm>
+#include <cstdlib>
+#include <functional>
+
+namespace tqr {
+
+// ----------------------------------------------------------------- weights
+double kind_weight(int kind) {
+  switch (kind) {
+    case K_GEQRT: return 4.0;
+    case K_TSQRT: return 6.0;
+    case K_TTQRT: return 2.0;
+    case K_UNMQR: return 6.0;
+    case K_TSMQR: return 12.0;
+    case K_TTMQR: return 6.0;
+    case K_TRSM: return 1.0;  // nb^3 flops
+    case K_GEMM: return 6.0;  // 2 nb^3 flops
+    default: return 0.0;
+  }
+}
+
+// ------------------------------------------------------------ graph build
+namespace {
+
+struct ItemState {
+  int32_t writer = -1;
+  std::vector<int32_t> readers;
+};
+
+class Builder {
+ public:
+  Builder(const GraphSpec &s, bool keep_structure)
+      : spec_(s), keep_(keep_structure), p_(s.p), q_(s.q), qt_(s.q + s.nbcols),
+        tri_((size_t)s.p * s.q, 0), zero_((size_t)s.p * s.q, 0.0), geqrt_((size_t)s.p * s.q, 0.0) {
+    const int smax = std::max(s.stripes, s.stripes_b);
+    smax_ = smax;
+    x_.resize((size_t)p_ * qt_ * smax);
+    u_.resize((size_t)p_ * q_);
+    l_.resize((size_t)p_ * q_);
+    tg_.resize((size_t)p_ * q_);
+    tk_.resize((size_t)p_ * q_);
+  }
+
+  Graph &graph() { return g_; }
+  const std::vector<double> &zero_times() const { return zero_; }
+  const std::vector<double> &geqrt_times() const { return geqrt_; }
+
+  // Kernels that the first column needs before any elimination (TT only:
+  // algorithm alg.elimTR with k = 0 triangularises every tile of column 1).
+  void start() {
+    if (spec_.solve) return;
+    if (spec_.family == FAM_TT)
+      for (int i = 0; i < p_; i++) factor_row(i, 0);
+  }
+
+  void elim(const Elim &e) {
+    const int i = e.i, piv = e.piv, k = e.k;
+    if (spec_.family == FAM_TT) {
+      zero(K_TTQRT, K_TTMQR, i, piv, k);
+      if (k + 1 < q_) factor_row(i, k + 1);
+    } else {
+      if (!tri_[idx(piv, k)]) factor_row(piv, k);
+      if (tri_[idx(i, k)])
+        zero(K_TTQRT, K_TTMQR, i, piv, k);
+      else
+        zero(K_TSQRT, K_TSMQR, i, piv, k);
+    }
+  }
+
+  void end() {
+    if (spec_.solve) return;
+    // The last diagonal tile of a square tile matrix is never a pivot in
+    // the hybrid family; it still has to be triangularised.
+    if (spec_.family == FAM_HYBRID && p_ == q_ && !tri_[idx(q_ - 1, q_ - 1)])
+      factor_row(q_ - 1, q_ - 1);
+  }
+
+  // Back-substitution R X = B over the tile columns of B: for k = q-1..0,
+  // X(k) = R(k,k)^{-1} B(k), then B(i) -= R(i,k) X(k) for i < k.
+  void solve() {
+    for (int jb = 0; jb < spec_.nbcols; jb++)
+      for (int s = 0; s < spec_.stripes_b; s++)
+        for (int k = q_ - 1; k >= 0; k--) {
+          emit(K_TRSM, k, k, k, q_ + jb, s, {&u_[idx(k, k)]}, {xitem(k, q_ + jb, s)});
+          for (int i = k - 1; i >= 0; i--)
+            emit(K_GEMM, i, i, k, q_ + jb, s, {&u_[idx(i, k)], xitem(k, q_ + jb, s)},
+                 {xitem(i, q_ + jb, s)});
+        }
+  }
+
+ private:
+  size_t idx(int i, int k) const { return (size_t)i * q_ + k; }
+  ItemState *xitem(int i, int j, int s) { return &x_[((size_t)i * qt_ + j) * smax_ + s]; }
+  int stripes_of(int j) const { return j < q_ ? spec_.stripes : spec_.stripes_b; }
+
+  // Target columns of the updates that follow a factor kernel of column k.
+  template <typename F>
+  void for_targets(int k, F f) {
+    if (spec_.panels)
+      for (int j = k + 1; j < q_; j++) f(j);
+    if (spec_.b_updates)
+      for (int j = q_; j < qt_; j++) f(j);
+  }
+
+  void factor_row(int i, int k) {
+    if (spec_.panels) {
+      std::vector<ItemState *> w = {&u_[idx(i, k)], &l_[idx(i, k)], &tg_[idx(i, k)]};
+      for (int s = 0; s < spec_.stripes; s++) w.push_back(xitem(i, k, s));
+      geqrt_[idx(i, k)] = emit(K_GEQRT, i, i, k, k, 0, {}, w);
+    }
+    tri_[idx(i, k)] = 1;
+    for_targets(k, [&](int j) {
+      for (int s = 0; s < stripes_of(j); s++)
+        emit(K_UNMQR, i, i, k, j, s, {&l_[idx(i, k)], &tg_[idx(i, k)]}, {xitem(i, j, s)});
+    });
+  }
+
+  void zero(int fk, int uk, int i, int piv, int k) {
+    if (spec_.panels) {
+      std::vector<ItemState *> w = {&u_[idx(piv, k)], &u_[idx(i, k)], &tk_[idx(i, k)]};
+      if (fk == K_TSQRT) {
+        w.push_back(&l_[idx(i, k)]);
+        for (int s = 0; s < spec_.stripes; s++) w.push_back(xitem(i, k, s));
+      }
+      zero_[idx(i, k)] = emit(fk, i, piv, k, k, 0, {}, w);
+    }
+    for_targets(k, [&](int j) {
+      for (int s = 0; s < stripes_of(j); s++) {
+        std::vector<ItemState *> r = {&u_[idx(i, k)], &tk_[idx(i, k)]};
+        if (uk == K_TSMQR) r.push_back(&l_[idx(i, k)]);
+        emit(uk, i, piv, k, j, s, r, {xitem(piv, j, s), xitem(i, j, s)});
+      }
+    });
+  }
+
+  // Appends one task; `rd` are read-only items, `wr` read-write items.
+  // Returns the task's earliest finish.
+  double emit(int kind, int i, int piv, int k, int j, int s, std::vector<ItemState *> rd,
+              std::vector<ItemState *> wr) {
+    const int32_t id = (int32_t)g_.finish.size();
+    std::vector<int32_t> pr;
+    for (ItemState *it : rd)
+      if (it->writer >= 0) pr.push_back(it->writer);
+    for (ItemState *it : wr) {
+      if (it->writer >= 0) pr.push_back(it->writer);
+      for (int32_t r : it->readers) pr.push_back(r);
+    }
+    std::sort(pr.begin(), pr.end());
+    pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+    double w = kind_weight(kind);
+    if (kind >= K_UNMQR && kind <= K_TTMQR) w /= stripes_of(j);
+    if (kind == K_TRSM || kind == K_GEMM) w /= spec_.stripes_b;
+    double start = 0.0;
+    for (int32_t x : pr) start = std::max(start, g_.finish[x]);
+    const double fin = start + w;
+    g_.finish.push_back(fin);
+    g_.cp = std::max(g_.cp, fin);
+    g_.nedges += (int64_t)pr.size();
+    for (ItemState *it : rd) it->readers.push_back(id);
+    for (ItemState *it : wr) {
+      it->writer = id;
+      it->readers.clear();
+    }
+    if (keep_) {
+      Task t{};
+      t.kind = kind;
+      t.i = i;
+      t.piv = piv;
+      t.k = k;
+      t.j = j;
+      t.stripe = s;
+      g_.tasks.push_back(t);
+      g_.preds.push_back(std::move(pr));
+      g_.weight.push_back(w);
+    }
+    return fin;
+  }
+
+  GraphSpec spec_;
+  bool keep_;
+  int p_, q_, qt_, smax_ = 1;
+  std::vector<ItemState> x_, u_, l_, tg_, tk_;
+  std::vector<char> tri_;
+  std::vector<double> zero_, geqrt_;
+  Graph g_;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- lists
+
+// Sameh-Kuck / FlatTree: the diagonal row zeroes every tile below it.
+static void list_flat(int p, int q, std::vector<Elim> &out) {
+  for (int k = 0; k < std::min(p, q); k++)
+    for (int i = k + 1; i < p; i++) out.push_back({i, k, k});
+}
+
+// BinaryTree: pairwise reduction of rows k..p-1 anchored at row k; at
+// distance h the row k + d (d an odd multiple of h) is zeroed by k + d - h.
+static void list_binary(int p, int q, std::vector<Elim> &out) {
+  for (int k = 0; k < std::min(p, q); k++) {
+    const int rows = p - k;
+    for (int h = 1; h < rows; h <<= 1)
+      for (int d = h; d < rows; d += h << 1) out.push_back({k + d, k + d - h, k});
+  }
+}
+
+// Fibonacci scheme of order 1 (Modi-Clarke): in column k the row at
+// relative position r = i - k + 1 (1-based) belongs to group y(r), the least
+// y with r <= y(y+1)/2 + 1.  Groups are zeroed from the bottom (largest y)
+// up; a group of z consecutive rows is zeroed by the z rows just above it.
+static void list_fibonacci(int p, int q, std::vector<Elim> &out) {
+  for (int k = 0; k < std::min(p, q); k++) {
+    std::vector<std::vector<int>> groups;  // groups[y-1] = rows (ascending)
+    int y = 1;
+    for (int i = k + 1; i < p; i++) {
+      const int r = i - k + 1;
+      while (r > y * (y + 1) / 2 + 1) y++;
+      if ((int)groups.size() < y) groups.resize(y);
+      groups[y - 1].push_back(i);
+    }
+    for (int gi = (int)groups.size() - 1; gi >= 0; gi--) {
+      const int z = (int)groups[gi].size();
+      for (int i : groups[gi]) out.push_back({i, i - z, k});
+    }
+  }
+}
+
+// Greedy (algorithm alg.tiled-greedy).  Per column j the counters nT (tiles
+// triangularised) and nZ (tiles zeroed) grow from the bottom row up.  At
+// each step, columns are visited from right to left; column j can
+// triangularise the tiles zeroed in column j-1 at earlier steps, and zeroes
+// half of its triangular-but-live tiles, the bottom ones, each with the
+// row `half` places above.  The number of new zeros uses the updated nT of
+// this step.
+static void list_greedy(int p, int q, std::vector<Elim> &out) {
+  const int last = std::min(q, p - 1) - 1;  // last column with eliminations
+  if (last < 0) return;
+  std::vector<int> nT(q, 0), nZ(q, 0);
+  while (nZ[last] < p - 1 - last) {
+    for (int j = q - 1; j >= 0; j--) {
+      const int t = (j == 0) ? p : nZ[j - 1];
+      const int half = (t - nZ[j]) / 2;
+      for (int a = 0; a < half; a++) {
+        const int row = p - 1 - nZ[j] - a;
+        out.push_back({row, row - half, j});
+      }
+      nT[j] = t;
+      nZ[j] += half;
+    }
+  }
+}
+
+// PlasmaTree(BS): domains of BS consecutive rows starting at the diagonal
+// row (the last one truncated); a flat tree inside each domain, then a
+// binary tree across the domain heads.
+static void list_plasma(int p, int q, int bs, std::vector<Elim> &out) {
+  if (bs < 1) bs = 1;
+  for (int k = 0; k < std::min(p, q); k++) {
+    for (int h = k; h < p; h += bs)
+      for (int i = h + 1; i < std::min(p, h + bs); i++) out.push_back({i, h, k});
+    const int heads = (p - 1 - k) / bs + 1;
+    for (int h = 1; h < heads; h <<= 1)
+      for (int d = h; d < heads; d += h << 1) out.push_back({k + d * bs, k + (d - h) * bs, k});
+  }
+}
+
+// ASAP on one column (definition def.optiter with w = TTQRT's weight): rows
+// become available when their GEQRT ends; whenever at least two available
+// rows are idle, the bottom 2s of them are paired, the upper s zeroing the
+// lower s in order; a pivot is busy for one TTQRT.
+static void asap_column(int k, const std::vector<double> &ready, std::vector<Elim> &out) {
+  const int p = (int)ready.size();
+  const double w = kind_weight(K_TTQRT);
+  std::vector<double> busy(p, 0.0);
+  std::vector<char> live(p, 0);
+  int nlive = 0;
+  for (int r = k; r < p; r++) {
+    live[r] = 1;
+    nlive++;
+  }
+  double t = 1e300;
+  for (int r = k; r < p; r++) t = std::min(t, ready[r]);
+  std::vector<int> av;
+  while (nlive > 1) {
+    av.clear();
+    for (int r = k; r < p; r++)
+      if (live[r] && ready[r] <= t && busy[r] <= t) av.push_back(r);
+    const int s = (int)av.size() / 2;
+    const int base = (int)av.size() - 2 * s;
+    for (int a = 0; a < s; a++) {
+      const int piv = av[base + a], row = av[base + s + a];
+      out.push_back({row, piv, k});
+      busy[piv] = t + w;
+      live[row] = 0;
+      nlive--;
+    }
+    double nt = 1e300;
+    for (int r = k; r < p; r++) {
+      if (!live[r]) continue;
+      if (ready[r] > t) nt = std::min(nt, ready[r]);
+      if (busy[r] > t) nt = std::min(nt, busy[r]);
+    }
+    if (nt >= 1e300) break;
+    t = nt;
+  }
+}
+
+// GrASAP(ia): Greedy on columns 0..q-ia-1, ASAP on the last ia columns
+// using the tiled GEQRT end times of the list built so far (definition
+// def.grasap).
+void asap_columns(int p, int q, int ia, std::vector<Elim> &out) {
+  std::vector<Elim> greedy;
+  list_greedy(p, q, greedy);
+  GraphSpec spec;
+  spec.p = p;
+  spec.q = q;
+  Builder b(spec, false);
+  b.start();
+  for (const Elim &e : greedy)
+    if (e.k < q - ia) {
+      out.push_back(e);
+      b.elim(e);
+    }
+  for (int k = std::max(0, q - ia); k < std::min(q, p - 1); k++) {
+    std::vector<double> ready(p, 0.0);
+    for (int r = k; r < p; r++) ready[r] = b.geqrt_times()[(size_t)r * q + k];
+    const size_t before = out.size();
+    asap_column(k, ready, out);
+    for (size_t e = before; e < out.size(); e++) b.elim(out[e]);
+  }
+}
+
+std::vector<Elim> make_list(int tree, int p, int q, int param) {
+  std::vector<Elim> out;
+  if (p < 1 || q < 1 || q > p) return out;
+  switch (tree) {
+    case TREE_FLAT: list_flat(p, q, out); break;
+    case TREE_BINARY: list_binary(p, q, out); break;
+    case TREE_FIBONACCI: list_fibonacci(p, q, out); break;
+    case TREE_GREEDY: list_greedy(p, q, out); break;
+    case TREE_GRASAP: asap_columns(p, q, param < 1 ? 1 : std::min(param, q), out); break;
+    case TREE_PLASMA: list_plasma(p, q, param, out); break;
+    case TREE_ASAP: asap_columns(p, q, q, out); break;
+    default: break;
+  }
+  return out;
+}
+
+Graph build_graph(const std::vector<Elim> &list, const GraphSpec &spec, std::vector<double> *zero_t,
+                  std::vector<double> *geqrt_t) {
+  Builder b(spec, true);
+  if (spec.solve) {
+    b.solve();
+  } else {
+    b.start();
+    for (const Elim &e : list) b.elim(e);
+    b.end();
+  }
+  if (zero_t) *zero_t = b.zero_times();
+  if (geqrt_t) *geqrt_t = b.geqrt_times();
+  return std::move(b.graph());
+}
+
+void finalize(Graph &g, bool priority) {
+  const int n = (int)g.tasks.size();
+  std::vector<std::vector<int32_t>> succ(n);
+  for (int t = 0; t < n; t++)
+    for (int32_t pr : g.preds[t]) succ[pr].push_back(t);
+  g.bottom.assign(n, 0.0);
+  for (int t = n - 1; t >= 0; t--) {  // list order is topological
+    double m = 0.0;
+    for (int32_t s : succ[t]) m = std::max(m, g.bottom[s]);
+    g.bottom[t] = g.weight[t] + m;
+  }
+  g.succ_off.assign(n + 1, 0);
+  g.succ.clear();
+  g.succ.reserve(g.nedges);
+  g.indeg0.assign(n, 0);
+  for (int t = 0; t < n; t++) {
+    std::vector<int32_t> &s = succ[t];
+    if (priority)
+      std::stable_sort(s.begin(), s.end(), [&](int32_t a, int32_t b) { return g.bottom[a] > g.bottom[b]; });
+    g.succ_off[t] = (int32_t)g.succ.size();
+    for (int32_t x : s) g.succ.push_back(x);
+    g.indeg0[t] = (int32_t)g.preds[t].size();
+  }
+  g.succ_off[n] = (int32_t)g.succ.size();
+  g.ready0.clear();
+  for (int t = 0; t < n; t++)
+    if (g.indeg0[t] == 0) g.ready0.push_back(t);
+  if (priority)
+    std::stable_sort(g.ready0.begin(), g.ready0.end(),
+                     [&](int32_t a, int32_t b) { return g.bottom[a] > g.bottom[b]; });
+  g.order.resize(n);
+  for (int t = 0; t < n; t++) g.order[t] = t;
+}
+
+bool validate(const Graph &g) {
+  const int n = (int)g.tasks.size();
+  if ((int)g.succ_off.size() != n + 1 || (int)g.indeg0.size() != n) return false;
+  std::vector<int32_t> deg(n, 0);
+  for (int t = 0; t < n; t++)
+    for (int e = g.succ_off[t]; e < g.succ_off[t + 1]; e++) {
+      const int32_t s = g.succ[e];
+      if (s <= t || s >= n) return false;  // successors come later in list order
+      deg[s]++;
+    }
+  for (int t = 0; t < n; t++)
+    if (deg[t] != g.indeg0[t]) return false;
+  std::vector<int32_t> stack(g.ready0.begin(), g.ready0.end());
+  int seen = 0;
+  while (!stack.empty()) {
+    const int32_t t = stack.back();
+    stack.pop_back();
+    seen++;
+    for (int e = g.succ_off[t]; e < g.succ_off[t + 1]; e++)
+      if (--deg[g.succ[e]] == 0) stack.push_back(g.succ[e]);
+  }
+  return seen == n;
+}
+
+}  // namespace tqr

@@ -1,0 +1,79 @@
+// Host-side scheduling layer: elimination lists and the task graph that the
+// device executor runs.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "tqr_types.h"
+
+namespace tqr {
+
+// One elimination elim(i, piv, k) of algorithm alg.QR, 0-based.
+struct Elim {
+  int i, piv, k;
+};
+
+enum TreeId { TREE_FLAT = 0, TREE_BINARY = 1, TREE_FIBONACCI = 2, TREE_GREEDY = 3,
+              TREE_GRASAP = 4, TREE_PLASMA = 5, TREE_ASAP = 6 };
+enum KernelFamily { FAM_TT = 0, FAM_HYBRID = 1 };
+
+// Elimination list of a tree for p x q tiles (p >= q >= 1); param is the
+// PlasmaTree domain size or the i of GrASAP(i).  Empty on bad input.
+std::vector<Elim> make_list(int tree, int p, int q, int param);
+
+// Task weights of table tab.kernels (unit nb^3/3); the solve kernels are
+// weighted by their flops in the same unit.
+double kind_weight(int kind);
+
+// Task graph of the tiled algorithm.
+//
+// The elimination list is expanded, in list order, into kernels following
+// algorithm alg.elimTR (TT family) or the hybrid rule (a row is
+// triangularised at its first use as a pivot, a square tile is zeroed with
+// TSQRT/TSMQR as in algorithm alg.elimSQ, a triangle with TTQRT/TTMQR).
+// Dependencies are derived from the data each kernel reads and writes, in
+// that sequential order (read-after-write, write-after-read,
+// write-after-write), over these data items:
+//   X(i,j,s)  stripe s of tile (i,j) as an update target,
+//   U(i,k)    the upper triangle of a factored tile (R, or TT reflectors),
+//   L(i,k)    its strict lower part (GEQRT reflectors),
+//   TG(i,k)   GEQRT's T, TK(i,k) the T of the kernel that zeroes (i,k).
+// Splitting a tile update into stripes is exact: Q^T acts column by column.
+struct GraphSpec {
+  int p = 1, q = 1;      // tile rows / tile columns of A
+  int family = FAM_TT;
+  int stripes = 1;       // update tasks per target tile of A
+  int nbcols = 0;        // tile columns of B (right-hand sides)
+  int stripes_b = 1;     // update tasks per target tile of B
+  bool panels = true;    // emit the factor kernels (and A-column updates)
+  bool b_updates = false;  // emit updates of the B columns
+  bool solve = false;    // emit only the back-substitution R X = B
+};
+
+struct Graph {
+  std::vector<Task> tasks;                  // in a topological (list) order
+  std::vector<std::vector<int32_t>> preds;  // deduplicated predecessors
+  std::vector<double> weight;               // per task, unit nb^3/3
+  std::vector<double> finish;               // earliest finish, unbounded processors
+  // filled by finalize():
+  std::vector<int32_t> succ_off, succ, indeg0, ready0, order;
+  std::vector<double> bottom;  // longest path from the task to an exit, incl. itself
+  int64_t nedges = 0;
+  double cp = 0.0;
+};
+
+// Builds the graph of `list` under `spec`.  zero_t / geqrt_t, when given
+// (p*q, row-major, 0-based), receive the earliest finish of the kernel that
+// zeroes / triangularises each tile.
+Graph build_graph(const std::vector<Elim> &list, const GraphSpec &spec,
+                  std::vector<double> *zero_t = nullptr, std::vector<double> *geqrt_t = nullptr);
+
+// Successor lists, dependency counts, bottom levels and the initial ready
+// order (highest bottom level first when `priority`, else list order).
+void finalize(Graph &g, bool priority);
+
+// Host-side check that the graph is acyclic and that dependency counts
+// match (a Kahn pass over the successor lists).
+bool validate(const Graph &g);
+
+}  // namespace tqr

@@ -1,0 +1,67 @@
+// Types shared by the host library and the device executor.
+#pragma once
+#include <stdint.h>
+
+namespace tqr {
+
+// The six tile kernels of table tab.kernels, plus the two tile kernels of
+// the back-substitution R X = C that finishes a least-squares solve.
+enum Kind : int32_t {
+  K_GEQRT = 0,  // factor square tile (i,k) into R and reflectors V, T
+  K_TSQRT = 1,  // zero square tile (i,k) with the triangle of row piv
+  K_TTQRT = 2,  // zero triangle (i,k) with the triangle of row piv
+  K_UNMQR = 3,  // apply GEQRT(i,k)'s Q^T to tile (i,j)
+  K_TSMQR = 4,  // apply TSQRT(i,piv,k)'s Q^T to tiles (piv,j), (i,j)
+  K_TTMQR = 5,  // apply TTQRT(i,piv,k)'s Q^T to tiles (piv,j), (i,j)
+  K_TRSM = 6,   // X(k,j) <- R(k,k)^{-1} X(k,j)
+  K_GEMM = 7,   // X(i,j) <- X(i,j) - R(i,k) X(k,j)
+  K_COUNT = 8
+};
+
+// One task of the executor's graph.  Tile coordinates are 0-based; column
+// j >= q addresses tile column j - q of the right-hand-side matrix B.  An
+// update task covers the column stripe [stripe * sw, (stripe + 1) * sw) of
+// its target tiles, sw = nb / stripes.
+struct Task {
+  int32_t kind;
+  int32_t i, piv, k, j;
+  int32_t stripe;
+  int32_t pad0, pad1;
+};
+
+// Executor control block at the start of the executor-state region.
+struct ExecCtl {
+  int32_t head;    // next queue slot to pop
+  int32_t tail;    // next queue slot to push
+  int32_t done;    // tasks finished
+  int32_t abort;   // set by the watchdog
+  int32_t error;   // 0 or TQR_INFO_TIMEOUT
+  int32_t pad[11];
+};
+
+// Everything the device needs for one launch.
+struct ExecArgs {
+  // graph (library-owned, read-only)
+  const Task *tasks;
+  const int32_t *succ_off;   // ntasks + 1
+  const int32_t *succ;       // successor lists
+  const int32_t *indeg0;     // initial dependency counts
+  const int32_t *ready0;     // initially ready tasks, priority order
+  int32_t ntasks, nready0;
+  // executor state (caller workspace)
+  ExecCtl *ctl;
+  int32_t *queue;   // ntasks slots
+  int32_t *indeg;   // working dependency counts
+  // problem
+  double *A;
+  int64_t lda, m, n;
+  double *B;        // right-hand sides (apply / solve), may be null
+  int64_t ldb, nrhs;
+  double *Tf;       // T factors: ((i*q + k)*2 + which) * ib * nb doubles
+  int32_t p, q, nb, ib;
+  int32_t sw;       // stripe width (columns per update task)
+  int32_t pad;
+  int64_t spin_limit;  // watchdog, in wall-clock ticks
+};
+
+}  // namespace tqr

@@ -1,0 +1,84 @@
+"""The product's elimination lists and critical paths (C++ in libtqr.so,
+host-only entry points) against the oracle, bit for bit, and against the
+thesis's printed values; plus the ABI check that every entry point that
+include/tqr.h declares is exported."""
+import re
+
+import pytest
+
+import paper_1303_3182_amd as T
+from oracle import trees as O
+
+SHAPES = [(1, 1), (2, 1), (2, 2), (4, 2), (8, 3), (15, 6), (16, 16), (20, 6), (33, 7), (40, 40),
+          (64, 8), (17, 13), (100, 3), (31, 31)]
+TREES = [("flat", 0), ("binary", 0), ("fibonacci", 0), ("greedy", 0), ("grasap", 0), ("grasap", 2),
+         ("asap", 0), ("plasma", 1), ("plasma", 3), ("plasma", 5)]
+
+
+@pytest.mark.parametrize("tree,param", TREES)
+def test_lists_identical(tree, param):
+    for p, q in SHAPES:
+        assert T.tqr_tree_list(tree, p, q, param) == O.elimination_list(tree, p, q, param), (tree, p, q)
+
+
+@pytest.mark.parametrize("kernels", [T.TT, T.HYBRID])
+@pytest.mark.parametrize("tree,param", TREES)
+def test_critical_paths_identical(tree, param, kernels):
+    for p, q in SHAPES:
+        cp, zero, counts = T.tqr_tree_cp(tree, p, q, param, kernels, want_zero=True)
+        ref = O.tiled(p, q, O.elimination_list(tree, p, q, param), kernels)
+        assert cp == ref["cp"], (tree, p, q)
+        assert zero == ref["zero"].tolist(), (tree, p, q)
+        assert counts == [ref["counts"][k] for k in O.KERNELS], (tree, p, q)
+
+
+def test_printed_values(golden):
+    """A few of the thesis's printed values straight from the product."""
+    assert T.tqr_tree_cp("greedy", 20, 6) == 136 and T.tqr_tree_cp("grasap", 20, 6) == 134
+    for row in golden("table_biggermat.txt"):
+        p, q, gr, asap = (int(v) for v in row)
+        if p <= 64:
+            assert T.tqr_tree_cp("greedy", p, q) == gr
+    for row in golden("p40_theory.txt")[::7]:
+        assert T.tqr_tree_cp("greedy", 40, int(row[1])) == int(row[2])
+        assert T.tqr_tree_cp("fibonacci", 40, int(row[1])) == int(row[7])
+        assert T.tqr_tree_cp("plasma", 40, int(row[1]), int(row[4])) == int(row[3])
+    _, zero, _ = T.tqr_tree_cp("greedy", 15, 6, want_zero=True)
+    tab = {}
+    for r in golden("tab_tiled.txt"):
+        if r[0] == "GREEDY":
+            tab[int(r[1])] = [int(v) for v in r[2:]]
+    for i, vals in tab.items():
+        assert zero[i - 1][:len(vals)] == vals
+
+
+def test_bad_arguments():
+    with pytest.raises(T.TqrError):
+        T.tqr_tree_list("greedy", 2, 3)
+    assert T.tqr_workspace_size(10, 20) == 0
+    assert T.tqr_workspace_size(100, 50, 0, T.default_opts(nb=48)) == 0
+
+
+def test_graph_stats_match_theorem_counts():
+    """Task counts of the executor graph follow theorem thm.flops (TT,
+    one stripe per tile)."""
+    for (p, q) in [(4, 2), (64, 8), (32, 32)]:
+        nb = 64
+        nt, ne = T.tqr_graph_stats(p * nb, q * nb, T.default_opts(nb=nb, tree="greedy", stripes=1))
+        geqrt = sum(p - k + 1 for k in range(1, q + 1))
+        ttqrt = geqrt - q
+        unmqr = sum((p - k + 1) * (q - k) for k in range(1, q + 1))
+        ttmqr = sum((p - k) * (q - k) for k in range(1, q + 1))
+        assert nt == geqrt + ttqrt + unmqr + ttmqr
+        assert ne > 0
+
+
+def test_header_symbols_exported():
+    import ctypes
+    import os
+    hdr = open(os.path.join(os.path.dirname(T.library_path()), "..", "include", "tqr.h")).read()
+    names = set(re.findall(r"^[a-z][^;/]*?\b(tqr_[a-z_0-9]+)\(", hdr, re.M))
+    assert {"tqr_factor", "tqr_apply_qt", "tqr_lstsq"} <= names
+    L = ctypes.CDLL(T.library_path())
+    for nm in sorted(names):
+        assert hasattr(L, nm), nm
