@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark of the tiled QR path on one MI355X.
+
+Workload: FP64 least squares on a tall-skinny matrix, m = 16384, n = 2048,
+tile nb = 256 (64 x 8 tiles), entries i.i.d. N(0,1) (seeded, synthetic),
+GrASAP elimination tree, TT kernels.  One step is the whole hot path on one
+batch: restore A from a pristine device copy, factor A = QR (elimination
+list + task graph are cached; every kernel runs in the persistent
+executor), apply Q^T to b, and back-substitute R x = (Q^T b)(1:n).
+
+value = 2 n^2 (m - n/3) / (seconds per step), in TFLOP/s: only the QR flops
+are counted although the step also applies Q^T and solves.  Inputs are
+resident in HBM when the timed region starts.
+
+The JSON line also carries the roofline of the dominant kernel (the
+persistent executor of the factorization, timed with HIP events on its own
+stream inside the timed region) and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QR TFLOP/s (2n²(m−n/3)) plain FP64 vs mixed+refined at equal FP64 error"
+PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix peak
+
+
+def log(msg):
+    sys.stderr.write("[bench] %s\n" % msg)
+    sys.stderr.flush()
+
+
+def qr_flops(m, n):
+    return 2.0 * n * n * (m - n / 3.0)
+
+
+def cpu_baseline(A0, ncols):
+    """The FP64 oracle (unblocked Householder, numpy) on the first `ncols`
+    columns of the workload matrix: a bounded sample, rate in TFLOP/s of the
+    same flop formula."""
+    from oracle import householder as H
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        cores = 1
+    S = A0[:, :ncols].copy(order="F")
+    t0 = time.perf_counter()
+    H.qr(S)
+    dt = time.perf_counter() - t0
+    m = S.shape[0]
+    return {"value": qr_flops(m, ncols) / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores),
+            "kind": "oracle", "seconds": dt,
+            "sample": "unblocked FP64 Householder QR of the first %d columns of the %dx%d workload "
+                      "matrix (%d x %d)" % (ncols, m, A0.shape[1], m, ncols)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--m", type=int, default=16384)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--nb", type=int, default=256)
+    ap.add_argument("--ib", type=int, default=32)
+    ap.add_argument("--tree", default="grasap")
+    ap.add_argument("--kernels", default="tt")
+    ap.add_argument("--stripes", type=int, default=0)
+    ap.add_argument("--cpu-sample-cols", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the design note on sharding is in DESIGN.md); use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1303_3182_amd as T
+    import synth
+
+    m, n, nb = args.m, args.n, args.nb
+    log("workload %dx%d nb=%d tree=%s kernels=%s" % (m, n, nb, args.tree, args.kernels))
+    A0 = synth.gaussian(m, n, 1)
+    b0 = synth.gaussian_rhs(m, 1, 1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    opts = T.default_opts(nb=nb, ib=args.ib, tree=args.tree, kernels=args.kernels, stripes=args.stripes)
+    A_src = T.colmajor(A0, dev)
+    b_src = T.colmajor(b0, dev)
+    A = T.colmajor(A0, dev)
+    b = T.colmajor(b0, dev)
+    W = T.workspace(m, n, 1, opts, dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    ev = []
+
+    def step(timed):
+        A.copy_(A_src)
+        b.copy_(b_src)
+        if timed:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+        T.factor(A, opts, T=W, info=info)
+        if timed:
+            e1.record()
+            ev.append((e0, e1))
+        T.apply_qt(A, W, b, opts)
+        T.solve_r(A, W, b, opts, info=info)
+
+    for w in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log("warmup done (%d steps)" % args.warmup)
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    factor_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
+    log("timed %d steps: %.3f ms/step, factor kernel %.3f ms" % (args.steps, ms, factor_ms))
+    if int(info.item()) != 0:
+        raise SystemExit("executor reported info=%d" % int(info.item()))
+
+    # accuracy of the last step's solution: Stewart's one-sided backward
+    # error bound ||A^T r|| / (||A||_F ||r||) in extended precision
+    x = b[:n, 0].cpu().numpy()
+    Al = A0.astype(np.longdouble)
+    r = b0[:, 0].astype(np.longdouble) - Al @ x.astype(np.longdouble)
+    be = float(np.linalg.norm((Al.T @ r).astype(np.float64)) /
+               (np.linalg.norm(A0) * np.linalg.norm(r.astype(np.float64))))
+
+    flops = qr_flops(m, n)
+    achieved = flops / (factor_ms / 1e3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": flops / (ms / 1e3) / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "FP64 tiled-QR least squares, tall-skinny %dx%d, nb=%d (%dx%d tiles), "
+                               "N(0,1) entries, seed 1" % (m, n, nb, -(-m // nb), -(-n // nb)),
+                   "m": m, "n": n, "nb": nb, "ib": args.ib, "tree": args.tree,
+                   "kernels": args.kernels, "precision": "plain FP64"},
+        "factor_ms": factor_ms,
+        "ls_backward_error": be,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
+                     "kernel": "exec_persistent (factorization task graph)"},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a %d-column sample" % args.cpu_sample_cols)
+        out["cpu_baseline"] = cpu_baseline(A0, args.cpu_sample_cols)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -132,6 +132,16 @@ int tqr_apply_qt(int64_t m, int64_t n, const double *A, int64_t lda, void *T, si
                  int64_t nrhs, double *B, int64_t ldb, const tqr_opts *o, int32_t *info,
                  hipStream_t stream);
 
+/* Back-substitution R X = C with the R held in the upper triangle of the
+ * first n rows of A by a previous factor call (same m, n, options): C is
+ * rows 0..n-1 of B (nrhs columns, ldb >= m), overwritten by X; rows n..m-1
+ * of B are not touched.  Least squares needs it after tqr_apply_qt
+ * (chapter introduction: x = R^{-1} (Q^T b)(1:n)).  info: NULL or a device
+ * int32 receiving 0 or j > 0 if R(j,j) is exactly zero. */
+int tqr_solve_r(int64_t m, int64_t n, const double *A, int64_t lda, void *T, size_t t_bytes,
+                int64_t nrhs, double *B, int64_t ldb, const tqr_opts *o, int32_t *info,
+                hipStream_t stream);
+
 /* Least squares min ||A x - b||_2 for each of nrhs right-hand sides
  * (chapter introduction: QR solves the m-equation, n-unknown least-squares
  * problem): X = R^{-1} (Q^T B)(1:n, :).  A (m x n, lda) and B (m x nrhs,
@@ -168,6 +178,26 @@ int64_t tqr_tree_cp(int32_t tree, int32_t p, int32_t q, int32_t param, int32_t k
 int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, int64_t *nedges);
 
 const char *tqr_strerror(int code);
+
+/* ---------------------------------------------------------- diagnostics */
+
+/* Debug only, not thread-safe: while buf is non-NULL every executor launch
+ * records, for each task t < cap, four int64 at buf + 4t: start and end
+ * (device wall clock, hipDeviceAttributeWallClockRate kHz), the workgroup
+ * and the hardware CU id that ran it.  buf is a device buffer owned by the
+ * caller.  Pass NULL to stop. */
+void tqr_debug_trace(int64_t *buf, int64_t cap);
+
+/* Debug only: the executor's task table for a plan (kind 0 factor, 1 apply
+ * with nrhs columns, 2 solve) as 8 int32 per task: kind, i, piv, k, j,
+ * stripe, number of successors, number of predecessors.  Returns the task
+ * count (tasks written only if cap >= count). */
+int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o,
+                    int32_t *tasks, int64_t cap);
+
+/* Debug only: successor lists (CSR) of the factor plan; off has ntasks+1
+ * entries, succ cap entries.  Returns the number of edges or -1. */
+int tqr_debug_succ(int64_t m, int64_t n, const tqr_opts *o, int32_t *off, int32_t *succ, int64_t cap);
 
 #ifdef __cplusplus
 }

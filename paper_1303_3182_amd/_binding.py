@@ -50,12 +50,16 @@ def lib():
             "tqr_factor": (ctypes.c_int, [i64, i64, i32, i32, vp, vp, vp]),
             "tqr_factor_ex": (ctypes.c_int, [i64, i64, vp, i64, vp, sz, op, vp, vp]),
             "tqr_apply_qt": (ctypes.c_int, [i64, i64, vp, i64, vp, sz, i64, vp, i64, op, vp, vp]),
+            "tqr_solve_r": (ctypes.c_int, [i64, i64, vp, i64, vp, sz, i64, vp, i64, op, vp, vp]),
             "tqr_lstsq_work_size": (sz, [i64, i64, i64, op]),
             "tqr_lstsq": (ctypes.c_int, [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, op, vp, vp]),
             "tqr_tree_list": (i64, [i32, i32, i32, i32, i32p, i32p, i32p, i64]),
             "tqr_tree_cp": (i64, [i32, i32, i32, i32, i32, i64p, i64p]),
             "tqr_graph_stats": (ctypes.c_int, [i64, i64, op, i64p, i64p]),
             "tqr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+            "tqr_debug_trace": (None, [vp, i64]),
+            "tqr_debug_graph": (ctypes.c_int, [i64, i64, i64, i32, op, i32p, i64]),
+            "tqr_debug_succ": (ctypes.c_int, [i64, i64, op, i32p, i32p, i64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -108,6 +112,11 @@ def tqr_apply_qt(m, n, A, lda, T, t_bytes, nrhs, B, ldb, opts, info, stream):
                                      stream), "tqr_apply_qt")
 
 
+def tqr_solve_r(m, n, A, lda, T, t_bytes, nrhs, B, ldb, opts, info, stream):
+    return _check(lib().tqr_solve_r(m, n, A, lda, T, t_bytes, nrhs, B, ldb, _opts_ptr(opts), info,
+                                    stream), "tqr_solve_r")
+
+
 def tqr_lstsq_work_size(m, n, nrhs, opts=None):
     return int(lib().tqr_lstsq_work_size(m, n, nrhs, _opts_ptr(opts)))
 
@@ -152,3 +161,29 @@ def tqr_graph_stats(m, n, opts=None):
     _check(lib().tqr_graph_stats(m, n, _opts_ptr(opts), ctypes.byref(nt), ctypes.byref(ne)),
            "tqr_graph_stats")
     return nt.value, ne.value
+
+
+def debug_trace(buf_ptr, cap):
+    """Record per-task clock stamps into a device int64 buffer (debug)."""
+    lib().tqr_debug_trace(buf_ptr, cap)
+
+
+def debug_graph(m, n, opts=None, nrhs=0, kind=0):
+    """Task table of a plan as a list of (kind, i, piv, k, j, stripe, nsucc, npred)."""
+    L = lib()
+    nt = L.tqr_debug_graph(m, n, nrhs, kind, _opts_ptr(opts), None, 0)
+    if nt < 0:
+        raise TqrError("tqr_debug_graph failed (%d)" % nt)
+    buf = (ctypes.c_int32 * (8 * max(nt, 1)))()
+    L.tqr_debug_graph(m, n, nrhs, kind, _opts_ptr(opts), buf, nt)
+    return [tuple(buf[8 * t:8 * t + 8]) for t in range(nt)]
+
+
+def debug_succ(m, n, opts=None):
+    L = lib()
+    tasks = debug_graph(m, n, opts)
+    ne = sum(t[6] for t in tasks)
+    off = (ctypes.c_int32 * (len(tasks) + 1))()
+    succ = (ctypes.c_int32 * max(ne, 1))()
+    L.tqr_debug_succ(m, n, _opts_ptr(opts), off, succ, ne)
+    return list(off), list(succ)

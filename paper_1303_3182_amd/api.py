@@ -60,6 +60,14 @@ def apply_qt(A, T, Bm, opts=None, info=None):
     return Bm
 
 
+def solve_r(A, T, Bm, opts=None, info=None):
+    """B[:n] <- R^{-1} B[:n] with R from factor() (same opts)."""
+    m, n = A.shape
+    B.tqr_solve_r(m, n, A.data_ptr(), _ld(A), T.data_ptr(), T.numel(), Bm.shape[1], Bm.data_ptr(),
+                  _ld(Bm), opts, None if info is None else info.data_ptr(), _stream())
+    return Bm
+
+
 def lstsq(A, Bm, opts=None, X=None, work=None, info=None):
     """Least-squares solution X (n x nrhs) of min ||A X - B||; A, B untouched."""
     m, n = A.shape

@@ -14,8 +14,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + CSRC, "-I" + INCLUDE, "-I/opt/rocm/include", "-Wall", "-Wno-unused-result"]
 # Device code: never emit packed FP32 instructions (hardware notes).
+# MFMA accumulators in VGPRs: avoids AGPR<->VGPR copies around guarded MFMA blocks.
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-ffp-contract=fast"]
+          "-ffp-contract=fast", "-mllvm", "-amdgpu-mfma-vgpr-form"]
 HOST_SOURCES = ["graph.cpp", "api.cpp"]
 DEVICE_SOURCES = ["kernels.hip"]
 

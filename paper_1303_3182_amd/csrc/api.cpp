@@ -60,6 +60,8 @@ std::map<PlanKey, std::shared_ptr<HostPlan>> g_host;
 std::map<std::pair<int, PlanKey>, DevicePlan> g_dev;
 std::map<int, int> g_grid;
 std::map<std::pair<int, int>, int64_t> g_spin;
+int64_t *g_trace = nullptr;
+int64_t g_trace_cap = 0;
 
 std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
   {
@@ -250,7 +252,10 @@ int run_plan(int kind, int64_t m, int64_t n, double *A, int64_t lda, double *B, 
   a.nb = nb;
   a.ib = r.ib;
   a.sw = nb / (kind == PK_FACTOR ? key.stripes : key.stripes_b);
+  a.dma_ok = ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda % 2) == 0) ? 1 : 0;
   a.spin_limit = spin_limit_ticks(dev);
+  a.trace = g_trace;
+  a.trace_cap = g_trace_cap;
   const int grid = grid_size(dev, nb, r.ib);
   hipError_t e = launch_exec(a, r.exec == TQR_EXEC_SEQUENTIAL ? 1 : 0, grid, hp->g.order.data(),
                              info, stream);
@@ -289,7 +294,10 @@ size_t tqr_workspace_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o)
   if (resolve(o, &r)) return 0;
   const int64_t p = cdiv(m, r.nb), q = cdiv(n, r.nb);
   int64_t nt = plan_tasks(PK_FACTOR, m, n, 0, r);
-  if (nrhs > 0) nt = std::max(nt, plan_tasks(PK_APPLY, m, n, nrhs, r));
+  if (nrhs > 0) {
+    nt = std::max(nt, plan_tasks(PK_APPLY, m, n, nrhs, r));
+    nt = std::max(nt, plan_tasks(PK_SOLVE, m, n, nrhs, r));
+  }
   return kHeader + align_up(tfactor_bytes(p, q, r.nb, r.ib)) + state_bytes(nt);
 }
 
@@ -332,6 +340,25 @@ int tqr_apply_qt(int64_t m, int64_t n, const double *A, int64_t lda, void *T, si
   int rc = resolve(o, &r);
   if (rc) return rc;
   return run_plan(PK_APPLY, m, n, const_cast<double *>(A), lda, B, ldb, nrhs, T, t_bytes, r, info,
+                  stream);
+}
+
+int tqr_solve_r(int64_t m, int64_t n, const double *A, int64_t lda, void *T, size_t t_bytes,
+                int64_t nrhs, double *B, int64_t ldb, const tqr_opts *o, int32_t *info,
+                hipStream_t stream) {
+  if (m < 1) return -1;
+  if (n < 1 || n > m) return -2;
+  if (!A) return -3;
+  if (lda < m) return -4;
+  if (!T) return -5;
+  if (nrhs < 0) return -7;
+  if (!B && nrhs > 0) return -8;
+  if (ldb < m) return -9;
+  if (nrhs == 0) return TQR_OK;
+  Resolved r;
+  int rc = resolve(o, &r);
+  if (rc) return rc;
+  return run_plan(PK_SOLVE, m, n, const_cast<double *>(A), lda, B, ldb, nrhs, T, t_bytes, r, info,
                   stream);
 }
 
@@ -429,6 +456,48 @@ int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, in
   if (ntasks) *ntasks = (int64_t)hp->g.tasks.size();
   if (nedges) *nedges = hp->g.nedges;
   return hp->valid ? TQR_OK : TQR_E_INTERNAL;
+}
+
+void tqr_debug_trace(int64_t *buf, int64_t cap) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_trace = buf;
+  g_trace_cap = buf ? cap : 0;
+}
+
+int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *tasks,
+                    int64_t cap) {
+  if (m < 1 || n < 1 || n > m) return -1;
+  Resolved r;
+  int rc = resolve(o, &r);
+  if (rc) return rc;
+  const int nbcols = (kind == PK_FACTOR) ? 0 : (int)cdiv(nrhs, r.nb);
+  auto hp = host_plan(make_key(kind, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), nbcols, r));
+  const int64_t nt = (int64_t)hp->g.tasks.size();
+  if (tasks && cap >= nt)
+    for (int64_t t = 0; t < nt; t++) {
+      const Task &x = hp->g.tasks[t];
+      int32_t *o8 = tasks + 8 * t;
+      o8[0] = x.kind;
+      o8[1] = x.i;
+      o8[2] = x.piv;
+      o8[3] = x.k;
+      o8[4] = x.j;
+      o8[5] = x.stripe;
+      o8[6] = hp->g.succ_off[t + 1] - hp->g.succ_off[t];
+      o8[7] = hp->g.indeg0[t];
+    }
+  return (int)nt;
+}
+
+int tqr_debug_succ(int64_t m, int64_t n, const tqr_opts *o, int32_t *off, int32_t *succ, int64_t cap) {
+  Resolved r;
+  int rc = resolve(o, &r);
+  if (rc) return rc;
+  auto hp = host_plan(make_key(PK_FACTOR, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), 0, r));
+  if ((int64_t)hp->g.succ.size() > cap) return -1;
+  std::copy(hp->g.succ_off.begin(), hp->g.succ_off.end(), off);
+  std::copy(hp->g.succ.begin(), hp->g.succ.end(), succ);
+  return (int)hp->g.succ.size();
 }
 
 const char *tqr_strerror(int code) {

@@ -33,8 +33,59 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ double shfl_xor(double v, int mask) {
-  return __shfl_xor(v, mask, 64);
+// Zeroes a loaded value unless `on`, with integer masking.  A select
+// between a load and 0 would be turned by the backend into a branch around
+// the load followed by a full wait, serialising every load of a loop; the
+// mask keeps the (clamped, always in-bounds) load unconditional.
+__device__ __forceinline__ double zmask(double v, bool on) {
+  return __longlong_as_double(__double_as_longlong(v) & -(long long)on);
+}
+
+// threadIdx.x through a volatile register move: values derived from it are
+// then recomputed inside each task instead of being hoisted out of the
+// persistent loop (where hundreds of them would stay live and spill).
+__device__ __forceinline__ int opaque_tid() {
+  int t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+  return t;
+}
+
+// Reciprocal and square root from the hardware approximations, refined by
+// one Newton step each (a few ulps instead of the correctly rounded library
+// sequences, which cost several hundred cycles on the panel's serial path).
+__device__ __forceinline__ double hrcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double hsqrt(double x) {
+  // x > 0 here (a sum of squares with a nonzero term)
+  const double y = __builtin_amdgcn_rsq(x);  // ~1/sqrt(x)
+  const double h = 0.5 * y;
+  double s = x * y;
+  const double r = fma(-s, h, 0.5);  // Goldschmidt step
+  s = fma(s, r, s);
+  const double hh = fma(h, r, h);
+  const double d = fma(-s, s, x);
+  return fma(d, hh, s);
+}
+
+// Sum over aligned groups of G lanes (G = 8 or 16) with DPP lane moves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(G == 8 || G == 16, "group of 8 or 16 lanes");
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+  v += dpp_d<0x141>(v);  // row_half_mirror: lane i <-> 7 - i in each 8
+  if (G == 16) v += dpp_d<0x140>(v);  // row_mirror: lane i <-> 15 - i
+  return v;
 }
 
 // --------------------------------------------------------------- smem
@@ -42,22 +93,91 @@ template <int NB, int IB, int WC>
 struct Smem {
   static constexpr int LDV = NB + 2;   // VL column stride
   static constexpr int LDT = IB + 1;   // TL / Ys column stride
-  static constexpr int LDW = WC + 16;  // WP / YL row stride
-  double VL[IB * LDV];                 // reflectors of one block: VL[cc*LDV + r]
-  double TL[IB * LDT];                 // T of one block: TL[cc*LDT + r] = T(r,cc)
-  double WP[4 * IB * LDW];             // per-wave partial W: WP[(w*IB + kk)*LDW + n]
-  double YL[IB * LDW];                 // T^T W: YL[kk*LDW + n]
-  double vbuf[2][NB + IB];             // panel: current reflector
+  static constexpr int LDW = WC + 16;  // YL row stride
+  // reflectors of one block, two buffers: VL[buf][cc*LDV + r].  The solve
+  // kernels use VL[1] as YL (a block row of X, YL[kk*LDW + n]).
+  static constexpr int VSZ = (IB * LDV > IB * LDW) ? IB * LDV : IB * LDW;
+  double VL[2][VSZ];
+  double TL[2][IB * LDT];              // T of one block: TL[buf][cc*LDT + r] = T(r,cc)
+  double vbuf[2][NB + IB];             // panel: current reflector (zero past the panel)
   double Ys[IB * LDT];                 // panel: Ys[jj*LDT + j] = v_jj^T v_j
   double tau[IB];
   int task;
+  __device__ double *YL() { return VL[1]; }
 };
 
 enum { M_UNM = 0, M_TT = 1, M_TS = 2 };
 
+// Columns of a chunk handled by one apply pass: 4 waves x 16 columns.
+constexpr int CHUNK = 64;
+
+// Loads reflector block b of a tile into VL (rows [rlo, rhi) only), with
+// the structure of the mode applied: M_UNM unit lower triangular, M_TT
+// upper triangular including the diagonal, M_TS full.  Columns past vcols
+// and rows past vrows are zero (no reflector / zero padding).
+template <int NB, int IB, int WC, int MODE>
+__device__ __forceinline__ void stage_v(const double *__restrict__ V, int64_t ldv, int vrows, int vcols,
+                                        int b, int rlo, int rhi, double *VLb) {
+  constexpr int TPR = (NT / NB) > 0 ? NT / NB : 1;  // threads per row
+  constexpr int CPT = IB / TPR;                      // columns per thread
+  constexpr int LDV = Smem<NB, IB, WC>::LDV;
+  static_assert(CPT * TPR == IB, "IB must split over the threads of a row");
+  const int t_ = opaque_tid();
+  const int row = t_ % NB;
+  const int c0 = (t_ / NB) * CPT;
+  if (row >= rlo && row < rhi) {
+    const int rowc = min(row, vrows - 1);  // clamped: every load stays inside the tile
+#pragma unroll
+    for (int u = 0; u < CPT; u++) {
+      const int cc = c0 + u, col = b * IB + cc;
+      const int colc = min(col, vcols - 1);
+      const double ld = V[colc * ldv + rowc];
+      const bool in = row < vrows && col < vcols;
+      double v;
+      if (MODE == M_UNM)
+        v = (row == col) ? 1.0 : zmask(ld, row > col && in);
+      else if (MODE == M_TT)
+        v = zmask(ld, row <= col && in);
+      else
+        v = zmask(ld, in);
+      VLb[cc * LDV + row] = v;
+    }
+  }
+}
+
+// Asynchronous copy of the 128-row segments of reflector block b that meet
+// rows [rlo, rhi) straight into LDS (global_load_lds_dwordx4: each lane
+// moves two rows, no registers).  Only for full tiles with 16-byte aligned
+// columns; the triangular structure is applied when the operands are read.
+template <int NB, int IB, int WC>
+__device__ __forceinline__ void dma_v(const double *__restrict__ V, int64_t ldv, int b, int rlo, int rhi,
+                                      double *VLb) {
+  constexpr int SEG = 128;
+  constexpr int LDV = Smem<NB, IB, WC>::LDV;
+  const int wave = __builtin_amdgcn_readfirstlane(opaque_tid() >> 6);
+  const int lane = __lane_id();
+  const int s0 = rlo / SEG, s1 = (rhi + SEG - 1) / SEG, ns = s1 - s0;
+  for (int it = wave; it < IB * ns; it += NT / 64) {
+    const int cc = it / ns, seg = s0 + it % ns;
+    const double *gp = V + (int64_t)(b * IB + cc) * ldv + seg * SEG + 2 * lane;
+    __builtin_amdgcn_global_load_lds(gp, (__attribute__((address_space(3))) void *)(VLb + cc * LDV + seg * SEG),
+                                     16, 0, 0);
+  }
+}
+
+// Structure of reflector block b at (row, reflector column col), applied
+// to values read from VL when they were DMA'd raw (staged values are
+// already masked).
+template <int MODE>
+__device__ __forceinline__ double vmask(double v, int row, int col) {
+  if (MODE == M_UNM) return row > col ? v : (row == col ? 1.0 : 0.0);
+  if (MODE == M_TT) return row <= col ? v : 0.0;
+  return v;
+}
+
 // ===================================================== block reflector apply
 //
-// Applies reflector blocks b0..b1-1 of one tile to a chunk of at most WC
+// Applies reflector blocks b0..b1-1 of one tile to a chunk of at most CHUNK
 // columns:
 //   M_UNM: C2 <- Q^T C2 with V unit lower triangular (GEQRT's reflectors)
 //   M_TT : [C1; C2] <- Q^T [C1; C2], Q = I - [I; V2] T [I; V2]^T with V2
@@ -66,197 +186,186 @@ enum { M_UNM = 0, M_TT = 1, M_TS = 2 };
 // For block b (reflectors b*IB .. b*IB+IB-1):
 //   W = V_b^T C2 (+ C1[b rows] for TT/TS),  Y = T_b^T W,
 //   C2 -= V_b Y,  C1[b rows] -= Y.
-// C1/C2 stay in registers (MFMA accumulator layout) across all blocks; each
-// wave owns the 16-row blocks rb = wave + 4t.  With `prestaged`, VL/TL
-// already hold block b0 (one block only) and are not reloaded.
+// Each wave owns 16 columns of the chunk and every row of them, so W, Y and
+// C2 never leave its registers: C2 and W live in the MFMA accumulator
+// layout, whose register s is exactly the B operand of the K-step covering
+// rows 4s..4s+3 of a 16-row block.  The reflectors and T are shared through
+// LDS.  With `prestaged`, VL/TL already hold block b0 (one block only).
 template <int NB, int IB, int WC, int MODE>
-__device__ void apply_blocks(const double *__restrict__ V, int64_t ldv, int vrows, int vcols,
-                             const double *__restrict__ Tf, double *C1, int64_t ldc1,
-                             double *C2, int64_t ldc2, int c2rows, int ncols, int b0, int b1,
-                             bool prestaged, Smem<NB, IB, WC> &sm) {
+__device__ __forceinline__ void apply_chunk(const double *__restrict__ V, int64_t ldv, int vrows,
+                                            int vcols, const double *__restrict__ Tf, double *C1,
+                                            int64_t ldc1, double *C2, int64_t ldc2, int c2rows,
+                                            int ncols, int b0, int b1, bool prestaged, bool dma,
+                                            Smem<NB, IB, WC> &sm) {
   constexpr int NRB = NB / 16;
-  constexpr int RBW = (NRB + 3) / 4;
-  constexpr int NCB = WC / 16;
   constexpr int NMB = IB / 16;
   constexpr int LDV = Smem<NB, IB, WC>::LDV;
   constexpr int LDT = Smem<NB, IB, WC>::LDT;
-  constexpr int LDW = Smem<NB, IB, WC>::LDW;
-  const int tid = threadIdx.x;
-  const int w = tid >> 6;
+  const int tid = opaque_tid();
   const int lane = tid & 63;
   const int g = lane >> 4;
   const int c = lane & 15;
+  const int col = (tid >> 6) * 16 + c;  // this lane's column in the chunk
+  const bool ok = col < ncols;
 
-  // rows of C2 touched by the blocks
   const int r2lo = (MODE == M_UNM) ? b0 * IB : 0;
   const int r2hi = (MODE == M_TT) ? b1 * IB : NB;
-  const int r1lo = b0 * IB, r1hi = b1 * IB;
-
-  d4 c2[RBW][NCB];
-  d4 c1[RBW][NCB];
+  d4 c2[NRB];
+  const int colc = ok ? col : 0;  // clamped: loads of masked lanes stay inside the tile
 #pragma unroll
-  for (int t = 0; t < RBW; t++) {
-    const int rb = w + 4 * t;
-#pragma unroll
-    for (int cb = 0; cb < NCB; cb++) {
-      const int col = cb * 16 + c;
+  for (int rb = 0; rb < NRB; rb++) {
+    if (rb * 16 + 16 > r2lo && rb * 16 < r2hi) {
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int row = rb * 16 + 4 * r + g;
-        double v2 = 0.0, v1 = 0.0;
-        if (rb < NRB && col < ncols) {
-          if (row >= r2lo && row < r2hi && row < c2rows) v2 = C2[col * ldc2 + row];
-          if (MODE != M_UNM && row >= r1lo && row < r1hi) v1 = C1[col * ldc1 + row];
-        }
-        c2[t][cb][r] = v2;
-        c1[t][cb][r] = v1;
+        const double ld = C2[colc * ldc2 + min(row, c2rows - 1)];
+        c2[rb][r] = zmask(ld, ok && row >= r2lo && row < r2hi && row < c2rows);
+      }
+    } else {
+      c2[rb] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  }
+
+  // T of the next block, loaded into registers while the previous computes
+  constexpr int TPT = (IB * IB + NT - 1) / NT;
+  double tld[TPT];
+  auto load_t = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < TPT; q++) {
+      const int idx = min(tid + NT * q, IB * IB - 1);
+      tld[q] = Tf[(b * IB + idx / IB) * IB + idx % IB];
+    }
+  };
+  auto store_t = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < TPT; q++) {
+      const int idx = tid + NT * q;
+      if (idx < IB * IB) {
+        const int cc = idx / IB, r = idx % IB;
+        sm.TL[buf][cc * LDT + r] = zmask(tld[q], r <= cc);
       }
     }
+  };
+  auto v_rows = [&](int b, int &rlo, int &rhi) {
+    rlo = (MODE == M_UNM) ? b * IB : 0;
+    rhi = (MODE == M_TT) ? (b + 1) * IB : NB;
+  };
+  if (!prestaged) {
+    __syncthreads();  // earlier users of VL/TL are done
+    int rlo, rhi;
+    v_rows(b0, rlo, rhi);
+    if (dma) dma_v<NB, IB, WC>(V, ldv, b0, rlo, rhi, sm.VL[0]);
+    else stage_v<NB, IB, WC, MODE>(V, ldv, vrows, vcols, b0, rlo, rhi, sm.VL[0]);
+    load_t(b0);
   }
 
   for (int b = b0; b < b1; b++) {
-    // rows of V_b that can be nonzero
-    const int rlo = (MODE == M_UNM) ? b * IB : 0;
-    const int rhi = (MODE == M_TT) ? (b + 1) * IB : NB;
+    const int buf = prestaged ? 0 : ((b - b0) & 1);
+    int rlo, rhi;
+    v_rows(b, rlo, rhi);
     if (!prestaged) {
-      const int nr = rhi - rlo;
-      for (int idx = tid; idx < IB * nr; idx += NT) {
-        const int cc = idx / nr, r = rlo + idx % nr;
-        const int col = b * IB + cc;
-        // columns past the matrix hold no reflector (their tau is 0)
-        double v = 0.0;
-        if (MODE == M_UNM) {
-          if (r == col) v = 1.0;
-          else if (r > col && r < vrows && col < vcols) v = V[col * ldv + r];
-        } else if (MODE == M_TT) {
-          if (r <= col && r < vrows && col < vcols) v = V[col * ldv + r];
-        } else {
-          if (r < vrows && col < vcols) v = V[col * ldv + r];
-        }
-        sm.VL[cc * LDV + r] = v;
-      }
-      for (int idx = tid; idx < IB * IB; idx += NT) {
-        const int cc = idx / IB, r = idx % IB;
-        sm.TL[cc * LDT + r] = (r <= cc) ? Tf[(b * IB + cc) * IB + r] : 0.0;
-      }
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this block's DMA / loads landed
+      store_t(buf);
       __syncthreads();
+      if (b + 1 < b1) {  // prefetch the next block into the other buffer
+        int nlo, nhi;
+        v_rows(b + 1, nlo, nhi);
+        if (dma) dma_v<NB, IB, WC>(V, ldv, b + 1, nlo, nhi, sm.VL[buf ^ 1]);
+        else stage_v<NB, IB, WC, MODE>(V, ldv, vrows, vcols, b + 1, nlo, nhi, sm.VL[buf ^ 1]);
+        load_t(b + 1);
+      }
     }
-
-    // ---- W partial of this wave: V_b[own rows]^T C2[own rows]
-    d4 wacc[NMB][NCB];
+    const double *VLb = sm.VL[buf];
+    const double *TLb = sm.TL[buf];
+    const int dlo = b * IB, dhi = (b + 1) * IB;  // rows of the block's triangle
+    // W = V_b^T C2, accumulated in two partial sums (even / odd row blocks)
+    // so that four independent MFMA chains are in flight
+    d4 w[NMB], w2[NMB];
 #pragma unroll
-    for (int mb = 0; mb < NMB; mb++)
+    for (int mb = 0; mb < NMB; mb++) {
+      w[mb] = d4{0.0, 0.0, 0.0, 0.0};
+      w2[mb] = d4{0.0, 0.0, 0.0, 0.0};
+    }
 #pragma unroll
-      for (int cb = 0; cb < NCB; cb++) wacc[mb][cb] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int t = 0; t < RBW; t++) {
-      const int rb = w + 4 * t;
-      if (rb < NRB && rb * 16 >= rlo && rb * 16 < rhi) {
+    for (int rb = 0; rb < NRB; rb++) {
+      if (rb * 16 >= rlo && rb * 16 < rhi) {
+        const bool diag = dma && MODE != M_TS && rb * 16 >= dlo && rb * 16 < dhi;
 #pragma unroll
         for (int s = 0; s < 4; s++) {
-          const int row = rb * 16 + 4 * s + g;  // K index g of K-step s
 #pragma unroll
           for (int mb = 0; mb < NMB; mb++) {
-            const double a = sm.VL[(mb * 16 + c) * LDV + row];
-#pragma unroll
-            for (int cb = 0; cb < NCB; cb++) wacc[mb][cb] = mfma(a, c2[t][cb][s], wacc[mb][cb]);
+            double a = VLb[(mb * 16 + c) * LDV + rb * 16 + 4 * s + g];
+            if (diag) a = vmask<MODE>(a, rb * 16 + 4 * s + g, dlo + mb * 16 + c);
+            if (rb & 1)
+              w2[mb] = mfma(a, c2[rb][s], w2[mb]);
+            else
+              w[mb] = mfma(a, c2[rb][s], w[mb]);
           }
         }
       }
     }
+#pragma unroll
+    for (int mb = 0; mb < NMB; mb++) w[mb] += w2[mb];
+    // W += C1[b rows]  (the identity top part of the TT/TS reflectors)
+    d4 c1[NMB];
     if (MODE != M_UNM) {
-      // W += C1[b*IB .. b*IB+IB) (identity top part of the reflectors)
 #pragma unroll
       for (int mb = 0; mb < NMB; mb++) {
-        const int rb1 = b * (IB / 16) + mb;
-        if ((rb1 & 3) == w) {
-          const int t1 = rb1 >> 2;
 #pragma unroll
-          for (int t = 0; t < RBW; t++)
-            if (t == t1)
+        for (int r = 0; r < 4; r++) {
+          const int row = b * IB + mb * 16 + 4 * r + g;
+          c1[mb][r] = zmask(C1[colc * ldc1 + row], ok);
+        }
+        w[mb] += c1[mb];
+      }
+    }
+    // Y = T_b^T W  (T_b upper triangular: block (mb, kb) is zero for kb > mb)
+    d4 y[NMB];
 #pragma unroll
-              for (int cb = 0; cb < NCB; cb++) wacc[mb][cb] += c1[t][cb];
+    for (int mb = 0; mb < NMB; mb++) {
+      y[mb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kb = 0; kb <= mb; kb++)
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+          const double a = TLb[(mb * 16 + c) * LDT + kb * 16 + 4 * s + g];
+          y[mb] = mfma(a, w[kb][s], y[mb]);
+        }
+    }
+    if (MODE != M_UNM) {
+#pragma unroll
+      for (int mb = 0; mb < NMB; mb++) {
+        c1[mb] -= y[mb];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int row = b * IB + mb * 16 + 4 * r + g;
+          if (ok) C1[col * ldc1 + row] = c1[mb][r];
         }
       }
     }
+    // C2 -= V_b Y
 #pragma unroll
-    for (int mb = 0; mb < NMB; mb++)
+    for (int rb = 0; rb < NRB; rb++) {
+      if (rb * 16 >= rlo && rb * 16 < rhi) {
+        const bool diag = dma && MODE != M_TS && rb * 16 >= dlo && rb * 16 < dhi;
 #pragma unroll
-      for (int cb = 0; cb < NCB; cb++)
+        for (int kb = 0; kb < NMB; kb++)
 #pragma unroll
-        for (int r = 0; r < 4; r++)
-          sm.WP[(w * IB + mb * 16 + 4 * r + g) * LDW + cb * 16 + c] = wacc[mb][cb][r];
-    __syncthreads();
-
-    // ---- W = sum of the partials (in place into WP[0])
-    for (int idx = tid; idx < IB * WC; idx += NT) {
-      const int kk = idx / WC, n = idx % WC;
-      double s = sm.WP[(0 * IB + kk) * LDW + n];
-      s += sm.WP[(1 * IB + kk) * LDW + n];
-      s += sm.WP[(2 * IB + kk) * LDW + n];
-      s += sm.WP[(3 * IB + kk) * LDW + n];
-      sm.WP[kk * LDW + n] = s;
-    }
-    __syncthreads();
-    // ---- Y = T_b^T W
-    for (int idx = tid; idx < IB * WC; idx += NT) {
-      const int i = idx / WC, n = idx % WC;
-      double s = 0.0;
-      for (int kk = 0; kk <= i; kk++) s += sm.TL[i * LDT + kk] * sm.WP[kk * LDW + n];
-      sm.YL[i * LDW + n] = s;
-    }
-    __syncthreads();
-
-    // ---- C2[own rows] -= V_b[own rows] Y ; C1[b rows] -= Y
-#pragma unroll
-    for (int t = 0; t < RBW; t++) {
-      const int rb = w + 4 * t;
-      if (rb < NRB && rb * 16 >= rlo && rb * 16 < rhi) {
-#pragma unroll
-        for (int ks = 0; ks < IB / 4; ks++) {
-          const double a = -sm.VL[(ks * 4 + g) * LDV + rb * 16 + c];
-#pragma unroll
-          for (int cb = 0; cb < NCB; cb++) {
-            const double bb = sm.YL[(ks * 4 + g) * LDW + cb * 16 + c];
-            c2[t][cb] = mfma(a, bb, c2[t][cb]);
+          for (int s = 0; s < 4; s++) {
+            double a = VLb[(kb * 16 + 4 * s + g) * LDV + rb * 16 + c];
+            if (diag) a = vmask<MODE>(a, rb * 16 + c, dlo + kb * 16 + 4 * s + g);
+            c2[rb] = mfma(-a, y[kb][s], c2[rb]);
           }
-        }
       }
     }
-    if (MODE != M_UNM) {
-#pragma unroll
-      for (int mb = 0; mb < NMB; mb++) {
-        const int rb1 = b * (IB / 16) + mb;
-        if ((rb1 & 3) == w) {
-          const int t1 = rb1 >> 2;
-#pragma unroll
-          for (int t = 0; t < RBW; t++)
-            if (t == t1)
-#pragma unroll
-              for (int cb = 0; cb < NCB; cb++)
-#pragma unroll
-                for (int r = 0; r < 4; r++)
-                  c1[t][cb][r] -= sm.YL[(mb * 16 + 4 * r + g) * LDW + cb * 16 + c];
-        }
-      }
-    }
-    __syncthreads();
   }
 
 #pragma unroll
-  for (int t = 0; t < RBW; t++) {
-    const int rb = w + 4 * t;
+  for (int rb = 0; rb < NRB; rb++) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; cb++) {
-      const int col = cb * 16 + c;
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int row = rb * 16 + 4 * r + g;
-        if (rb < NRB && col < ncols) {
-          if (row >= r2lo && row < r2hi && row < c2rows) C2[col * ldc2 + row] = c2[t][cb][r];
-          if (MODE != M_UNM && row >= r1lo && row < r1hi) C1[col * ldc1 + row] = c1[t][cb][r];
-        }
-      }
+    for (int r = 0; r < 4; r++) {
+      const int row = rb * 16 + 4 * r + g;
+      if (ok && row >= r2lo && row < r2hi && row < c2rows) C2[col * ldc2 + row] = c2[rb][r];
     }
   }
 }
@@ -273,17 +382,19 @@ __device__ void apply_blocks(const double *__restrict__ V, int64_t ldv, int vrow
 //          part, GEQRT's V, is left untouched).
 //   M_TS : R1 on top of the full square Vt; Vt becomes V2.
 // Panel rows: thread t owns panel column t / RG and rows g, g+RG, ...
-// (g = t % RG).  M_UNM panel row pr is tile row b*IB + pr; for TT/TS panel
-// rows [0, IB) are R1 rows b*IB + pr and rows [IB, ...) are Vt rows pr - IB.
+// (g = t % RG, RG = 256 / IB lanes, contiguous, reduced with DPP).  M_UNM
+// panel row pr is tile row b*IB + pr; for TT/TS panel rows [0, IB) are R1
+// rows b*IB + pr and rows [IB, ...) are Vt rows pr - IB.
 template <int NB, int IB, int WC, int MODE>
-__device__ void panel_tile(double *Vt, int64_t ldv, int vrows, double *R1, int64_t ldr,
-                           int ncols, double *Tout, Smem<NB, IB, WC> &sm) {
+__device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, double *R1,
+                                           int64_t ldr, int ncols, double *Tout,
+                                           Smem<NB, IB, WC> &sm) {
   constexpr int RG = NT / IB;
-  constexpr int PRU = (NB + IB + RG - 1) / RG;
+  constexpr int PRU = (MODE == M_UNM) ? NB / RG : (NB + IB) / RG;
   constexpr int NBLK = NB / IB;
   constexpr int LDV = Smem<NB, IB, WC>::LDV;
   constexpr int LDT = Smem<NB, IB, WC>::LDT;
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int jt = tid / RG;  // panel column of this thread
   const int g = tid % RG;
 
@@ -292,87 +403,92 @@ __device__ void panel_tile(double *Vt, int64_t ldv, int vrows, double *R1, int64
     const int col = col0 + jt;
     const int npr = (MODE == M_UNM) ? NB - col0 : (MODE == M_TT ? IB + col0 + IB : IB + NB);
     double x[PRU];
-    // ---- load the panel
+    // ---- load the panel (clamped addresses, then select)
 #pragma unroll
     for (int u = 0; u < PRU; u++) {
       const int pr = g + RG * u;
-      double v = 0.0;
-      if (pr < npr && col < ncols) {
-        if (MODE == M_UNM) {
-          const int row = col0 + pr;
-          if (row < vrows) v = Vt[col * ldv + row];
-        } else if (pr < IB) {
-          if (pr <= jt) v = R1[col * ldr + col0 + pr];
-        } else {
-          const int row = pr - IB;
-          if (row < vrows && (MODE == M_TS || row <= col)) v = Vt[col * ldv + row];
-        }
+      const int colc = min(col, ncols - 1);
+      double v;
+      if (MODE == M_UNM) {
+        const int row = col0 + pr;
+        v = zmask(Vt[colc * ldv + min(row, vrows - 1)], pr < npr && col < ncols && row < vrows);
+      } else if (pr < IB) {
+        v = zmask(R1[colc * ldr + col0 + pr], pr <= jt && col < ncols);
+      } else {
+        const int row = pr - IB;
+        v = zmask(Vt[colc * ldv + min(row, vrows - 1)],
+                  pr < npr && col < ncols && row < vrows && (MODE == M_TS || row <= col));
       }
       x[u] = v;
     }
+    // reflector entries past npr stay zero, so the loops below need no guard
+    for (int idx = tid; idx < 2 * RG * PRU; idx += NT) sm.vbuf[idx / (RG * PRU)][idx % (RG * PRU)] = 0.0;
+    // Panel rows of the reflector of step j: the top row j, and x2 rows in
+    // [x2lo(j), x2hi(j)).
+    auto x2lo = [&](int j) { return (MODE == M_UNM) ? j + 1 : IB; };
+    auto x2hi = [&](int j) { return (MODE == M_TT) ? min(npr, IB + col0 + j + 1) : npr; };
+    // norm of the next reflector column, computed by its own threads one
+    // step ahead (fused with their update)
+    double sig_n = 0.0, alpha_n = 0.0;
+    {
+      const int lo = x2lo(0), hi = x2hi(0);
+#pragma unroll
+      for (int u = 0; u < PRU; u++) {
+        const int pr = g + RG * u;
+        sig_n += (pr >= lo && pr < hi) ? x[u] * x[u] : 0.0;
+        alpha_n += (pr == 0) ? x[u] : 0.0;
+      }
+      sig_n = group_sum<RG>(sig_n);
+      alpha_n = group_sum<RG>(alpha_n);
+    }
+    __syncthreads();
 
     for (int j = 0; j < IB; j++) {
       const int buf = j & 1;
-      // role of panel row pr in step j: 1 = top (alpha), 2 = x2, 0 = none
-      auto role = [&](int pr) -> int {
-        if (pr >= npr) return 0;
-        if (MODE == M_UNM) return pr == j ? 1 : (pr > j ? 2 : 0);
-        if (pr < IB) return pr == j ? 1 : 0;
-        if (MODE == M_TS) return 2;
-        return (pr - IB <= col0 + j) ? 2 : 0;
-      };
+      const int lo = x2lo(j), hi = x2hi(j);
       if (jt == j) {
-        double sig = 0.0, alpha = 0.0;
-#pragma unroll
-        for (int u = 0; u < PRU; u++) {
-          const int ro = role(g + RG * u);
-          if (ro == 2) sig += x[u] * x[u];
-          if (ro == 1) alpha += x[u];
-        }
-#pragma unroll
-        for (int msk = 1; msk < RG; msk <<= 1) {
-          sig += shfl_xor(sig, msk);
-          alpha += shfl_xor(alpha, msk);
-        }
+        const double sig = sig_n, alpha = alpha_n;
         double tau = 0.0, beta = alpha, scale = 0.0;
         if (sig != 0.0) {
-          const double nrm = sqrt(alpha * alpha + sig);
+          const double nrm = hsqrt(alpha * alpha + sig);
           beta = (alpha >= 0.0) ? -nrm : nrm;
-          tau = (beta - alpha) / beta;
-          scale = 1.0 / (alpha - beta);
+          tau = (beta - alpha) * hrcp(beta);
+          scale = hrcp(alpha - beta);
         }
 #pragma unroll
         for (int u = 0; u < PRU; u++) {
           const int pr = g + RG * u;
-          const int ro = role(pr);
-          double vv = 0.0;
-          if (ro == 2) {
-            x[u] *= scale;
-            vv = x[u];
-          } else if (ro == 1) {
-            x[u] = beta;
-            vv = 1.0;
-          }
-          if (pr < npr) sm.vbuf[buf][pr] = vv;
+          const bool x2 = pr >= lo && pr < hi;
+          const double xs = x[u] * scale;
+          x[u] = x2 ? xs : ((pr == j) ? beta : x[u]);
+          sm.vbuf[buf][pr] = x2 ? xs : ((pr == j) ? 1.0 : 0.0);
         }
         if (g == 0) sm.tau[j] = tau;
       }
       __syncthreads();
       if (jt != j) {
-        double dot = 0.0;
+        double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-        for (int u = 0; u < PRU; u++) {
-          const int pr = g + RG * u;
-          if (pr < npr) dot += sm.vbuf[buf][pr] * x[u];
+        for (int u = 0; u < PRU; u += 2) {
+          d0 += sm.vbuf[buf][g + RG * u] * x[u];
+          if (u + 1 < PRU) d1 += sm.vbuf[buf][g + RG * (u + 1)] * x[u + 1];
         }
-#pragma unroll
-        for (int msk = 1; msk < RG; msk <<= 1) dot += shfl_xor(dot, msk);
+        const double dot = group_sum<RG>(d0 + d1);
         if (jt > j) {
           const double f = sm.tau[j] * dot;
+          // update, and the next step's norm for the column it belongs to
+          const int lo1 = x2lo(j + 1), hi1 = x2hi(j + 1);
+          double sg = 0.0, al = 0.0;
 #pragma unroll
           for (int u = 0; u < PRU; u++) {
             const int pr = g + RG * u;
-            if (pr < npr) x[u] -= f * sm.vbuf[buf][pr];
+            x[u] -= f * sm.vbuf[buf][pr];
+            sg += (pr >= lo1 && pr < hi1) ? x[u] * x[u] : 0.0;
+            al += (pr == j + 1) ? x[u] : 0.0;
+          }
+          if (jt == j + 1) {
+            sig_n = group_sum<RG>(sg);
+            alpha_n = group_sum<RG>(al);
           }
         } else if (g == 0) {
           sm.Ys[jt * LDT + j] = dot;  // v_jt^T v_j, jt < j
@@ -388,49 +504,46 @@ __device__ void panel_tile(double *Vt, int64_t ldv, int vrows, double *R1, int64
       if (MODE == M_UNM) {
         const int row = col0 + pr;
         if (row < vrows && col < ncols) Vt[col * ldv + row] = x[u];
-        sm.VL[jt * LDV + row] = (pr > jt) ? x[u] : (pr == jt ? 1.0 : 0.0);
+        sm.VL[0][jt * LDV + row] = (pr > jt) ? x[u] : (pr == jt ? 1.0 : 0.0);
       } else if (pr < IB) {
         if (pr <= jt && col < ncols) R1[col * ldr + col0 + pr] = x[u];
       } else {
         const int row = pr - IB;
         const bool mine = (MODE == M_TS) || row <= col;
         if (mine && row < vrows && col < ncols) Vt[col * ldv + row] = x[u];
-        sm.VL[jt * LDV + row] = mine ? x[u] : 0.0;
-      }
-    }
-    if (MODE == M_UNM) {
-      // rows above the block are not part of V_b
-      for (int idx = tid; idx < IB * col0; idx += NT) sm.VL[(idx / col0) * LDV + idx % col0] = 0.0;
-    } else if (MODE == M_TT) {
-      for (int idx = tid; idx < IB * (NB - col0 - IB); idx += NT) {
-        const int n2 = NB - col0 - IB;
-        sm.VL[(idx / n2) * LDV + col0 + IB + idx % n2] = 0.0;
+        sm.VL[0][jt * LDV + row] = mine ? x[u] : 0.0;
       }
     }
     __syncthreads();
-    // ---- T of the block: T(r,r) = tau_r, T(r,j) = -tau_j sum_c T(r,c) Ys(c,j)
-    if (tid < IB) {
-      const int r = tid;
-      sm.TL[r * LDT + r] = sm.tau[r];
-      for (int jj = r + 1; jj < IB; jj++) {
-        double s = 0.0;
-        for (int cc = r; cc < jj; cc++) s += sm.TL[cc * LDT + r] * sm.Ys[cc * LDT + jj];
-        sm.TL[jj * LDT + r] = -sm.tau[jj] * s;
+    // ---- T of the block: T(r,r) = tau_r, T(r,j) = -tau_j sum_{c<j} T(r,c) Ys(c,j).
+    //      Row r is computed by the RG lanes of panel column r (one wave
+    //      holds all of them, so no barrier is needed between the steps).
+    {
+      const int r = jt;
+      for (int jj = 0; jj < IB; jj++) {
+        double sp = 0.0;
+#pragma unroll
+        for (int q = 0; q < IB / RG; q++) {
+          const int cc = g + RG * q;
+          const double t = sm.TL[0][cc * LDT + r];
+          sp += (cc >= r && cc < jj) ? t * sm.Ys[cc * LDT + jj] : 0.0;
+        }
+        const double ssum = group_sum<RG>(sp);
+        const double tj = sm.tau[jj];
+        if (g == 0) sm.TL[0][jj * LDT + r] = (r == jj) ? tj : ((r < jj) ? -tj * ssum : 0.0);
       }
-      for (int jj = 0; jj < r; jj++) sm.TL[jj * LDT + r] = 0.0;
     }
     __syncthreads();
     for (int idx = tid; idx < IB * IB; idx += NT) {
       const int cc = idx / IB, r = idx % IB;
-      Tout[(col0 + cc) * IB + r] = sm.TL[cc * LDT + r];
+      Tout[(col0 + cc) * IB + r] = sm.TL[0][cc * LDT + r];
     }
     // ---- trailing update of the tile's remaining columns with block b
-    for (int cs = col0 + IB; cs < NB; cs += WC) {
-      const int nc = min(WC, ncols - cs);
-      if (nc <= 0) break;
-      apply_blocks<NB, IB, WC, MODE>(nullptr, 0, vrows, ncols, nullptr,
-                                     (MODE == M_UNM) ? nullptr : R1 + cs * ldr, ldr,
-                                     Vt + cs * ldv, ldv, vrows, nc, b, b + 1, true, sm);
+    for (int cs = col0 + IB; cs < ncols; cs += CHUNK) {
+      const int nc = min(CHUNK, ncols - cs);
+      apply_chunk<NB, IB, WC, MODE>(nullptr, 0, vrows, ncols, nullptr,
+                                    (MODE == M_UNM) ? nullptr : R1 + cs * ldr, ldr, Vt + cs * ldv,
+                                    ldv, vrows, nc, b, b + 1, true, false, sm);
     }
     __syncthreads();
   }
@@ -445,11 +558,11 @@ __device__ void panel_tile(double *Vt, int64_t ldv, int vrows, double *R1, int64
 //              updated on MFMA.  Rows >= nk (past n) are left untouched.
 // Both keep the chunk in registers in the MFMA accumulator layout.
 template <int NB, int IB, int WC>
-__device__ void gemm_tile(const double *R, int64_t ldr, int nk, const double *X, int64_t ldx,
+__device__ __forceinline__ void gemm_tile(const double *R, int64_t ldr, int nk, const double *X, int64_t ldx,
                           double *C, int64_t ldc, int crows, int ncols, Smem<NB, IB, WC> &sm) {
   constexpr int NRB = NB / 16, RBW = (NRB + 3) / 4, NCB = WC / 16;
   constexpr int LDV = Smem<NB, IB, WC>::LDV, LDW = Smem<NB, IB, WC>::LDW;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
+  const int tid = opaque_tid(), w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
   d4 acc[RBW][NCB];
 #pragma unroll
   for (int t = 0; t < RBW; t++)
@@ -463,11 +576,11 @@ __device__ void gemm_tile(const double *R, int64_t ldr, int nk, const double *X,
   for (int b = 0; b * IB < nk; b++) {
     for (int idx = tid; idx < IB * NB; idx += NT) {
       const int cc = idx / NB, r = idx % NB, kc = b * IB + cc;
-      sm.VL[cc * LDV + r] = (kc < nk) ? R[kc * ldr + r] : 0.0;
+      sm.VL[0][cc * LDV + r] = (kc < nk) ? R[kc * ldr + r] : 0.0;
     }
     for (int idx = tid; idx < IB * WC; idx += NT) {
       const int kk = idx / WC, n = idx % WC, kr = b * IB + kk;
-      sm.YL[kk * LDW + n] = (kr < nk && n < ncols) ? X[n * ldx + kr] : 0.0;
+      sm.YL()[kk * LDW + n] = (kr < nk && n < ncols) ? X[n * ldx + kr] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -476,10 +589,10 @@ __device__ void gemm_tile(const double *R, int64_t ldr, int nk, const double *X,
       if (rb < NRB) {
 #pragma unroll
         for (int ks = 0; ks < IB / 4; ks++) {
-          const double a = -sm.VL[(ks * 4 + g) * LDV + rb * 16 + c];
+          const double a = -sm.VL[0][(ks * 4 + g) * LDV + rb * 16 + c];
 #pragma unroll
           for (int cb = 0; cb < NCB; cb++)
-            acc[t][cb] = mfma(a, sm.YL[(ks * 4 + g) * LDW + cb * 16 + c], acc[t][cb]);
+            acc[t][cb] = mfma(a, sm.YL()[(ks * 4 + g) * LDW + cb * 16 + c], acc[t][cb]);
         }
       }
     }
@@ -497,11 +610,11 @@ __device__ void gemm_tile(const double *R, int64_t ldr, int nk, const double *X,
 }
 
 template <int NB, int IB, int WC>
-__device__ void trsm_tile(const double *R, int64_t ldr, int nk, double *X, int64_t ldx, int ncols,
+__device__ __forceinline__ void trsm_tile(const double *R, int64_t ldr, int nk, double *X, int64_t ldx, int ncols,
                           int row0, int32_t *singular, Smem<NB, IB, WC> &sm) {
   constexpr int NRB = NB / 16, RBW = (NRB + 3) / 4, NCB = WC / 16, NMB = IB / 16;
   constexpr int LDV = Smem<NB, IB, WC>::LDV, LDT = Smem<NB, IB, WC>::LDT, LDW = Smem<NB, IB, WC>::LDW;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
+  const int tid = opaque_tid(), w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
   d4 acc[RBW][NCB];
 #pragma unroll
   for (int t = 0; t < RBW; t++)
@@ -518,7 +631,7 @@ __device__ void trsm_tile(const double *R, int64_t ldr, int nk, double *X, int64
     for (int idx = tid; idx < IB * IB; idx += NT) {
       const int cc = idx / IB, r = idx % IB;
       const int gr = b * IB + r, gc = b * IB + cc;
-      sm.TL[cc * LDT + r] = (gr < nk && gc < nk && r <= cc) ? R[gc * ldr + gr] : 0.0;
+      sm.TL[0][cc * LDT + r] = (gr < nk && gc < nk && r <= cc) ? R[gc * ldr + gr] : 0.0;
     }
 #pragma unroll
     for (int mb = 0; mb < NMB; mb++) {
@@ -530,7 +643,7 @@ __device__ void trsm_tile(const double *R, int64_t ldr, int nk, double *X, int64
 #pragma unroll
             for (int cb = 0; cb < NCB; cb++)
 #pragma unroll
-              for (int r = 0; r < 4; r++) sm.YL[(mb * 16 + 4 * r + g) * LDW + cb * 16 + c] = acc[t][cb][r];
+              for (int r = 0; r < 4; r++) sm.YL()[(mb * 16 + 4 * r + g) * LDW + cb * 16 + c] = acc[t][cb][r];
     }
     __syncthreads();
     if (tid < WC) {
@@ -538,11 +651,11 @@ __device__ void trsm_tile(const double *R, int64_t ldr, int nk, double *X, int64
       for (int r = IB - 1; r >= 0; r--) {
         const int gr = b * IB + r;
         if (gr >= nk) continue;
-        double s = sm.YL[r * LDW + n];
-        for (int cc = r + 1; cc < IB && b * IB + cc < nk; cc++) s -= sm.TL[cc * LDT + r] * sm.YL[cc * LDW + n];
-        const double d = sm.TL[r * LDT + r];
+        double s = sm.YL()[r * LDW + n];
+        for (int cc = r + 1; cc < IB && b * IB + cc < nk; cc++) s -= sm.TL[0][cc * LDT + r] * sm.YL()[cc * LDW + n];
+        const double d = sm.TL[0][r * LDT + r];
         if (d == 0.0 && n == 0) atomicMin(singular, row0 + gr + 1);
-        sm.YL[r * LDW + n] = s / d;
+        sm.YL()[r * LDW + n] = s / d;
       }
     }
     __syncthreads();
@@ -556,13 +669,13 @@ __device__ void trsm_tile(const double *R, int64_t ldr, int nk, double *X, int64
 #pragma unroll
             for (int cb = 0; cb < NCB; cb++)
 #pragma unroll
-              for (int r = 0; r < 4; r++) acc[t][cb][r] = sm.YL[(mb * 16 + 4 * r + g) * LDW + cb * 16 + c];
+              for (int r = 0; r < 4; r++) acc[t][cb][r] = sm.YL()[(mb * 16 + 4 * r + g) * LDW + cb * 16 + c];
     }
     if (b > 0) {
       // rows above the block: X[0, b*IB) -= R[0, b*IB) x block b
       for (int idx = tid; idx < IB * b * IB; idx += NT) {
         const int cc = idx / (b * IB), r = idx % (b * IB), gc = b * IB + cc;
-        sm.VL[cc * LDV + r] = (gc < nk) ? R[gc * ldr + r] : 0.0;
+        sm.VL[0][cc * LDV + r] = (gc < nk) ? R[gc * ldr + r] : 0.0;
       }
       __syncthreads();
 #pragma unroll
@@ -571,10 +684,10 @@ __device__ void trsm_tile(const double *R, int64_t ldr, int nk, double *X, int64
         if (rb < NRB && rb * 16 < b * IB) {
 #pragma unroll
           for (int ks = 0; ks < IB / 4; ks++) {
-            const double a = -sm.VL[(ks * 4 + g) * LDV + rb * 16 + c];
+            const double a = -sm.VL[0][(ks * 4 + g) * LDV + rb * 16 + c];
 #pragma unroll
             for (int cb = 0; cb < NCB; cb++)
-              acc[t][cb] = mfma(a, sm.YL[(ks * 4 + g) * LDW + cb * 16 + c], acc[t][cb]);
+              acc[t][cb] = mfma(a, sm.YL()[(ks * 4 + g) * LDW + cb * 16 + c], acc[t][cb]);
           }
         }
       }
@@ -596,7 +709,7 @@ __device__ void trsm_tile(const double *R, int64_t ldr, int nk, double *X, int64
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
 template <int NB, int IB, int WC>
-__device__ void run_task(const ExecArgs &a, const Task &t, Smem<NB, IB, WC> &sm) {
+__device__ __forceinline__ void run_task(const ExecArgs &a, const Task &t, Smem<NB, IB, WC> &sm) {
   const int64_t lda = a.lda;
   auto tileA = [&](int i, int j) { return a.A + (int64_t)j * NB * lda + (int64_t)i * NB; };
   auto rowsOf = [&](int i) { return (int)min((int64_t)NB, a.m - (int64_t)i * NB); };
@@ -654,20 +767,21 @@ __device__ void run_task(const ExecArgs &a, const Task &t, Smem<NB, IB, WC> &sm)
   const int vcols = (int)min((int64_t)NB, a.n - (int64_t)t.k * NB);
   const int cbeg = t.stripe * a.sw;
   const int cend = imin(ncols, cbeg + a.sw);
-  for (int cs = cbeg; cs < cend; cs += WC) {
-    const int nc = imin(WC, cend - cs);
+  const bool dma = a.dma_ok && NB >= 128 && vrows == NB && vcols == NB;
+  for (int cs = cbeg; cs < cend; cs += CHUNK) {
+    const int nc = imin(CHUNK, cend - cs);
     double *C2 = base + (int64_t)cs * ld + (int64_t)t.i * NB;
     if (kind == K_UNMQR) {
-      apply_blocks<NB, IB, WC, M_UNM>(V, lda, vrows, vcols, Tof(t.i, t.k, 0), nullptr, 0, C2, ld,
-                                      vrows, nc, 0, NB / IB, false, sm);
+      apply_chunk<NB, IB, WC, M_UNM>(V, lda, vrows, vcols, Tof(t.i, t.k, 0), nullptr, 0, C2, ld,
+                                     vrows, nc, 0, NB / IB, false, dma, sm);
     } else {
       double *C1 = base + (int64_t)cs * ld + (int64_t)t.piv * NB;
       if (kind == K_TTMQR)
-        apply_blocks<NB, IB, WC, M_TT>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld, vrows,
-                                       nc, 0, NB / IB, false, sm);
+        apply_chunk<NB, IB, WC, M_TT>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld, vrows,
+                                      nc, 0, NB / IB, false, dma, sm);
       else
-        apply_blocks<NB, IB, WC, M_TS>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld, vrows,
-                                       nc, 0, NB / IB, false, sm);
+        apply_chunk<NB, IB, WC, M_TS>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld, vrows,
+                                      nc, 0, NB / IB, false, dma, sm);
     }
   }
 }
@@ -749,10 +863,18 @@ __global__ __launch_bounds__(NT, 1) void exec_persistent(ExecArgs a) {
     const int tid = __builtin_amdgcn_readfirstlane(sm.task);
     if (tid < 0) break;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int64_t tstart = a.trace ? (int64_t)wall_clock64() : 0;
     run_task<NB, IB, WC>(a, load_task(a.tasks + tid), sm);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
+      if (a.trace && tid < a.trace_cap) {
+        int64_t *tr = a.trace + 4 * (int64_t)tid;
+        tr[0] = tstart;
+        tr[1] = (int64_t)wall_clock64();
+        tr[2] = blockIdx.x;
+        tr[3] = (int64_t)__smid();
+      }
       for (int e = a.succ_off[tid]; e < a.succ_off[tid + 1]; e++) {
         const int s = a.succ[e];
         if (__hip_atomic_fetch_add(&a.indeg[s], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1) {
@@ -770,7 +892,16 @@ __global__ __launch_bounds__(NT, 1) void exec_persistent(ExecArgs a) {
 template <int NB, int IB, int WC>
 __global__ __launch_bounds__(NT, 1) void exec_one(ExecArgs a, int tid) {
   __shared__ Smem<NB, IB, WC> sm;
+  const int64_t tstart = a.trace ? (int64_t)wall_clock64() : 0;
   run_task<NB, IB, WC>(a, load_task(a.tasks + tid), sm);
+  __syncthreads();
+  if (a.trace && threadIdx.x == 0 && tid < a.trace_cap) {
+    int64_t *tr = a.trace + 4 * (int64_t)tid;
+    tr[0] = tstart;
+    tr[1] = (int64_t)wall_clock64();
+    tr[2] = blockIdx.x;
+    tr[3] = (int64_t)__smid();
+  }
 }
 
 __global__ void exec_finish(ExecArgs a, int32_t *info) {
@@ -809,17 +940,19 @@ static int occupancy_cfg() {
 // Stripe width granule (columns per register-resident chunk) of a config.
 int chunk_width(int nb, int ib) {
   (void)ib;
-  return nb >= 256 ? 32 : (nb >= 64 ? 64 : 32);
+  return nb < CHUNK ? nb : CHUNK;
 }
 
+#ifdef TQR_ONE_CONFIG
+#define TQR_CONFIGS(X) X(256, 32, 64)
+#else
 #define TQR_CONFIGS(X) \
-  X(32, 16, 32)        \
+  X(32, 16, 64)        \
   X(64, 16, 64)        \
   X(64, 32, 64)        \
-  X(128, 16, 64)       \
   X(128, 32, 64)       \
-  X(256, 16, 32)       \
-  X(256, 32, 32)
+  X(256, 32, 64)
+#endif
 
 // mode: 0 persistent, 1 sequential (one launch per task in the host-side
 // topological order `order`).

@@ -60,8 +60,10 @@ struct ExecArgs {
   double *Tf;       // T factors: ((i*q + k)*2 + which) * ib * nb doubles
   int32_t p, q, nb, ib;
   int32_t sw;       // stripe width (columns per update task)
-  int32_t pad;
+  int32_t dma_ok;   // A is 16-byte aligned with even lda: tiles may be DMA'd to LDS
   int64_t spin_limit;  // watchdog, in wall-clock ticks
+  int64_t *trace;      // optional: per task {start, end, workgroup, xcc}
+  int64_t trace_cap;   // tasks that fit in `trace`
 };
 
 }  // namespace tqr
