@@ -76,8 +76,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the design note on sharding is in DESIGN.md); use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the factorization runs on a single device "
+              "and there is no multi-GPU path; use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

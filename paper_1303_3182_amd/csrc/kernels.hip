@@ -381,16 +381,22 @@ __device__ __forceinline__ void apply_chunk(const double *__restrict__ V, int64_
 //          overwritten by the new R, Vt's upper triangle by V2 (its lower
 //          part, GEQRT's V, is left untouched).
 //   M_TS : R1 on top of the full square Vt; Vt becomes V2.
-// Panel rows: thread t owns panel column t / RG and rows g, g+RG, ...
-// (g = t % RG, RG = 256 / IB lanes, contiguous, reduced with DPP).  M_UNM
-// panel row pr is tile row b*IB + pr; for TT/TS panel rows [0, IB) are R1
-// rows b*IB + pr and rows [IB, ...) are Vt rows pr - IB.
+// Panel rows: thread t owns panel column jt = t / RG and rows g, g+RG, ...
+// (g = t % RG, RG = 256 / IB contiguous lanes, reduced with DPP).  Panel
+// rows are ordered so that the rows whose role changes during the block's
+// IB steps come first (the "head"); every later row is a reflector row at
+// every step (or zero padding), so the hot loops need no per-row masks:
+//   M_UNM: tile rows col0 + pr                       (head: the IB x IB diagonal block)
+//   M_TT : [R1 rows col0..col0+IB) [Vt rows col0..col0+IB) [Vt rows 0..col0)
+//   M_TS : [R1 rows col0..col0+IB) [Vt rows 0..NB)
 template <int NB, int IB, int WC, int MODE>
 __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, double *R1,
                                            int64_t ldr, int ncols, double *Tout,
                                            Smem<NB, IB, WC> &sm) {
   constexpr int RG = NT / IB;
   constexpr int PRU = (MODE == M_UNM) ? NB / RG : (NB + IB) / RG;
+  constexpr int UH = ((MODE == M_TT) ? 2 * IB : IB) / RG;  // head slots
+  constexpr int UT = IB / RG;                              // slots of panel rows < IB
   constexpr int NBLK = NB / IB;
   constexpr int LDV = Smem<NB, IB, WC>::LDV;
   constexpr int LDT = Smem<NB, IB, WC>::LDT;
@@ -401,43 +407,52 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
   for (int b = 0; b < NBLK; b++) {
     const int col0 = b * IB;
     const int col = col0 + jt;
-    const int npr = (MODE == M_UNM) ? NB - col0 : (MODE == M_TT ? IB + col0 + IB : IB + NB);
+    const int npr = (MODE == M_UNM) ? NB - col0 : (MODE == M_TT ? 2 * IB + col0 : IB + NB);
+    const int colc = min(col, ncols - 1);
+    const bool cok = col < ncols;
+    // tile row of panel row pr, and which matrix it lives in (true: R1)
+    auto prow = [&](int pr, bool &in_r1) {
+      in_r1 = (MODE != M_UNM) && pr < IB;
+      if (MODE == M_UNM) return col0 + pr;
+      if (pr < IB) return col0 + pr;
+      if (MODE == M_TT) return pr < 2 * IB ? col0 + pr - IB : pr - 2 * IB;
+      return pr - IB;
+    };
     double x[PRU];
-    // ---- load the panel (clamped addresses, then select)
+    // ---- load the panel (clamped addresses, masked with integer AND)
 #pragma unroll
     for (int u = 0; u < PRU; u++) {
       const int pr = g + RG * u;
-      const int colc = min(col, ncols - 1);
-      double v;
-      if (MODE == M_UNM) {
-        const int row = col0 + pr;
-        v = zmask(Vt[colc * ldv + min(row, vrows - 1)], pr < npr && col < ncols && row < vrows);
-      } else if (pr < IB) {
-        v = zmask(R1[colc * ldr + col0 + pr], pr <= jt && col < ncols);
+      bool r1;
+      const int row = prow(pr, r1);
+      if (r1) {
+        x[u] = zmask(R1[colc * ldr + row], pr <= jt && cok);
       } else {
-        const int row = pr - IB;
-        v = zmask(Vt[colc * ldv + min(row, vrows - 1)],
-                  pr < npr && col < ncols && row < vrows && (MODE == M_TS || row <= col));
+        const bool tri = (MODE == M_TT) && pr < 2 * IB;  // R2's diagonal block: upper part only
+        x[u] = zmask(Vt[colc * ldv + min(row, vrows - 1)],
+                     cok && pr < npr && row < vrows && (!tri || row <= col));
       }
-      x[u] = v;
     }
-    // reflector entries past npr stay zero, so the loops below need no guard
     for (int idx = tid; idx < 2 * RG * PRU; idx += NT) sm.vbuf[idx / (RG * PRU)][idx % (RG * PRU)] = 0.0;
-    // Panel rows of the reflector of step j: the top row j, and x2 rows in
-    // [x2lo(j), x2hi(j)).
-    auto x2lo = [&](int j) { return (MODE == M_UNM) ? j + 1 : IB; };
-    auto x2hi = [&](int j) { return (MODE == M_TT) ? min(npr, IB + col0 + j + 1) : npr; };
+    // role of a head slot at step j: 1 top, 2 reflector row, 0 none
+    auto head_role = [&](int pr, int j) -> int {
+      if (pr == j) return 1;
+      if (MODE == M_UNM) return pr > j ? 2 : 0;
+      if (MODE == M_TT) return (pr >= IB && pr - IB <= j) ? 2 : 0;
+      return 0;
+    };
     // norm of the next reflector column, computed by its own threads one
     // step ahead (fused with their update)
     double sig_n = 0.0, alpha_n = 0.0;
     {
-      const int lo = x2lo(0), hi = x2hi(0);
 #pragma unroll
-      for (int u = 0; u < PRU; u++) {
-        const int pr = g + RG * u;
-        sig_n += (pr >= lo && pr < hi) ? x[u] * x[u] : 0.0;
-        alpha_n += (pr == 0) ? x[u] : 0.0;
+      for (int u = 0; u < UH; u++) {
+        const int ro = head_role(g + RG * u, 0);
+        sig_n += zmask(x[u] * x[u], ro == 2);
+        alpha_n += zmask(x[u], ro == 1);
       }
+#pragma unroll
+      for (int u = UH; u < PRU; u++) sig_n = fma(x[u], x[u], sig_n);
       sig_n = group_sum<RG>(sig_n);
       alpha_n = group_sum<RG>(alpha_n);
     }
@@ -445,7 +460,6 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
 
     for (int j = 0; j < IB; j++) {
       const int buf = j & 1;
-      const int lo = x2lo(j), hi = x2hi(j);
       if (jt == j) {
         const double sig = sig_n, alpha = alpha_n;
         double tau = 0.0, beta = alpha, scale = 0.0;
@@ -456,12 +470,17 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
           scale = hrcp(alpha - beta);
         }
 #pragma unroll
-        for (int u = 0; u < PRU; u++) {
+        for (int u = 0; u < UH; u++) {
           const int pr = g + RG * u;
-          const bool x2 = pr >= lo && pr < hi;
+          const int ro = head_role(pr, j);
           const double xs = x[u] * scale;
-          x[u] = x2 ? xs : ((pr == j) ? beta : x[u]);
-          sm.vbuf[buf][pr] = x2 ? xs : ((pr == j) ? 1.0 : 0.0);
+          x[u] = (ro == 2) ? xs : ((ro == 1) ? beta : x[u]);
+          sm.vbuf[buf][pr] = (ro == 2) ? xs : ((ro == 1) ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int u = UH; u < PRU; u++) {
+          x[u] *= scale;
+          sm.vbuf[buf][g + RG * u] = x[u];
         }
         if (g == 0) sm.tau[j] = tau;
       }
@@ -470,24 +489,30 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
         double d0 = 0.0, d1 = 0.0;
 #pragma unroll
         for (int u = 0; u < PRU; u += 2) {
-          d0 += sm.vbuf[buf][g + RG * u] * x[u];
-          if (u + 1 < PRU) d1 += sm.vbuf[buf][g + RG * (u + 1)] * x[u + 1];
+          d0 = fma(sm.vbuf[buf][g + RG * u], x[u], d0);
+          if (u + 1 < PRU) d1 = fma(sm.vbuf[buf][g + RG * (u + 1)], x[u + 1], d1);
         }
         const double dot = group_sum<RG>(d0 + d1);
         if (jt > j) {
           const double f = sm.tau[j] * dot;
           // update, and the next step's norm for the column it belongs to
-          const int lo1 = x2lo(j + 1), hi1 = x2hi(j + 1);
-          double sg = 0.0, al = 0.0;
+          double sg = 0.0, sg2 = 0.0, al = 0.0;
 #pragma unroll
-          for (int u = 0; u < PRU; u++) {
+          for (int u = 0; u < UH; u++) {
             const int pr = g + RG * u;
-            x[u] -= f * sm.vbuf[buf][pr];
-            sg += (pr >= lo1 && pr < hi1) ? x[u] * x[u] : 0.0;
-            al += (pr == j + 1) ? x[u] : 0.0;
+            x[u] = fma(-f, sm.vbuf[buf][pr], x[u]);
+            const int ro = head_role(pr, j + 1);
+            sg += zmask(x[u] * x[u], ro == 2);
+            al += zmask(x[u], ro == 1);
+          }
+#pragma unroll
+          for (int u = UH; u < PRU; u++) {
+            x[u] = fma(-f, sm.vbuf[buf][g + RG * u], x[u]);
+            if (u & 1) sg2 = fma(x[u], x[u], sg2);
+            else sg = fma(x[u], x[u], sg);
           }
           if (jt == j + 1) {
-            sig_n = group_sum<RG>(sg);
+            sig_n = group_sum<RG>(sg + sg2);
             alpha_n = group_sum<RG>(al);
           }
         } else if (g == 0) {
@@ -501,36 +526,43 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
     for (int u = 0; u < PRU; u++) {
       const int pr = g + RG * u;
       if (pr >= npr) continue;
+      bool r1;
+      const int row = prow(pr, r1);
       if (MODE == M_UNM) {
-        const int row = col0 + pr;
-        if (row < vrows && col < ncols) Vt[col * ldv + row] = x[u];
+        if (row < vrows && cok) Vt[col * ldv + row] = x[u];
         sm.VL[0][jt * LDV + row] = (pr > jt) ? x[u] : (pr == jt ? 1.0 : 0.0);
-      } else if (pr < IB) {
-        if (pr <= jt && col < ncols) R1[col * ldr + col0 + pr] = x[u];
+      } else if (r1) {
+        if (pr <= jt && cok) R1[col * ldr + row] = x[u];
       } else {
-        const int row = pr - IB;
         const bool mine = (MODE == M_TS) || row <= col;
-        if (mine && row < vrows && col < ncols) Vt[col * ldv + row] = x[u];
+        if (mine && row < vrows && cok) Vt[col * ldv + row] = x[u];
         sm.VL[0][jt * LDV + row] = mine ? x[u] : 0.0;
       }
     }
     __syncthreads();
     // ---- T of the block: T(r,r) = tau_r, T(r,j) = -tau_j sum_{c<j} T(r,c) Ys(c,j).
-    //      Row r is computed by the RG lanes of panel column r (one wave
-    //      holds all of them, so no barrier is needed between the steps).
+    //      Row r is computed by the RG lanes of panel column r; lane g keeps
+    //      T(r, g + RG q) in register trow[q] (the reduction leaves the sum
+    //      in every lane of the group), so no lane reads what another lane
+    //      of its wave wrote to LDS without a barrier in between.
     {
       const int r = jt;
+      double trow[IB / RG];
+#pragma unroll
+      for (int q = 0; q < IB / RG; q++) trow[q] = 0.0;
+#pragma unroll
       for (int jj = 0; jj < IB; jj++) {
         double sp = 0.0;
 #pragma unroll
         for (int q = 0; q < IB / RG; q++) {
           const int cc = g + RG * q;
-          const double t = sm.TL[0][cc * LDT + r];
-          sp += (cc >= r && cc < jj) ? t * sm.Ys[cc * LDT + jj] : 0.0;
+          sp += zmask(trow[q] * sm.Ys[cc * LDT + jj], cc >= r && cc < jj);
         }
         const double ssum = group_sum<RG>(sp);
         const double tj = sm.tau[jj];
-        if (g == 0) sm.TL[0][jj * LDT + r] = (r == jj) ? tj : ((r < jj) ? -tj * ssum : 0.0);
+        const double v = (r == jj) ? tj : ((r < jj) ? -tj * ssum : 0.0);
+        if (g == jj % RG) trow[jj / RG] = v;
+        if (g == 0) sm.TL[0][jj * LDT + r] = v;
       }
     }
     __syncthreads();
