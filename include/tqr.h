@@ -145,7 +145,9 @@ int tqr_solve_r(int64_t m, int64_t n, const double *A, int64_t lda, void *T, siz
 /* Least squares min ||A x - b||_2 for each of nrhs right-hand sides
  * (chapter introduction: QR solves the m-equation, n-unknown least-squares
  * problem): X = R^{-1} (Q^T B)(1:n, :).  A (m x n, lda) and B (m x nrhs,
- * ldb) are not modified; X is n x nrhs (ldx >= n).  work must be
+ * ldb) are not modified; X is n x nrhs (ldx >= n).  Factorization, Q^T B
+ * and the back-substitution run as one task graph in one executor launch
+ * (B's tile columns are extra columns of the tiled matrix).  work must be
  * tqr_lstsq_work_size bytes.  With opts.update_dtype != TQR_F64 the
  * factorization uses low-precision updates and X is refined in FP64
  * against the caller's A (at most opts.max_refine steps); info then
@@ -188,8 +190,19 @@ const char *tqr_strerror(int code);
  * caller.  Pass NULL to stop. */
 void tqr_debug_trace(int64_t *buf, int64_t cap);
 
+/* Diagnostics: with timing enabled, every executor launch is bracketed by a
+ * pair of HIP events recorded on the launch's stream (the executor kernel
+ * alone, not the copies or resets around it).  tqr_debug_timing(1) starts a
+ * new measurement (dropping earlier events), tqr_debug_timing(0) stops.
+ * tqr_debug_timing_read waits for the recorded launches and returns their
+ * summed duration in milliseconds and their number.  Not thread-safe with
+ * respect to concurrent launches on several streams. */
+void tqr_debug_timing(int32_t enable);
+int tqr_debug_timing_read(double *ms_total, int64_t *launches);
+
 /* Debug only: the executor's task table for a plan (kind 0 factor, 1 apply
- * with nrhs columns, 2 solve) as 8 int32 per task: kind, i, piv, k, j,
+ * with nrhs columns, 2 solve, 3 the least-squares graph of tqr_lstsq) as 8
+ * int32 per task: kind, i, piv, k, j,
  * stripe, number of successors, number of predecessors.  Returns the task
  * count (tasks written only if cap >= count). */
 int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o,

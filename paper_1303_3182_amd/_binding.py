@@ -58,6 +58,8 @@ def lib():
             "tqr_graph_stats": (ctypes.c_int, [i64, i64, op, i64p, i64p]),
             "tqr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "tqr_debug_trace": (None, [vp, i64]),
+            "tqr_debug_timing": (None, [i32]),
+            "tqr_debug_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), i64p]),
             "tqr_debug_graph": (ctypes.c_int, [i64, i64, i64, i32, op, i32p, i64]),
             "tqr_debug_succ": (ctypes.c_int, [i64, i64, op, i32p, i32p, i64]),
         }
@@ -161,6 +163,20 @@ def tqr_graph_stats(m, n, opts=None):
     _check(lib().tqr_graph_stats(m, n, _opts_ptr(opts), ctypes.byref(nt), ctypes.byref(ne)),
            "tqr_graph_stats")
     return nt.value, ne.value
+
+
+def debug_timing(enable):
+    """Start (True) or stop (False) HIP-event timing of every executor launch."""
+    lib().tqr_debug_timing(1 if enable else 0)
+
+
+def debug_timing_read():
+    """(total milliseconds, number of launches) of the executor launches
+    timed since debug_timing(True); waits for them to finish."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(lib().tqr_debug_timing_read(ctypes.byref(ms), ctypes.byref(cnt)), "tqr_debug_timing_read")
+    return ms.value, cnt.value
 
 
 def debug_trace(buf_ptr, cap):

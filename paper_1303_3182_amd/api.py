@@ -68,6 +68,14 @@ def solve_r(A, T, Bm, opts=None, info=None):
     return Bm
 
 
+def lstsq_workspace(m, n, nrhs=1, opts=None, device="cuda"):
+    """Device workspace for lstsq (uint8 tensor of tqr_lstsq_work_size bytes)."""
+    nbytes = B.tqr_lstsq_work_size(m, n, nrhs, opts)
+    if nbytes == 0:
+        raise B.TqrError("invalid shape/options for lstsq")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
 def lstsq(A, Bm, opts=None, X=None, work=None, info=None):
     """Least-squares solution X (n x nrhs) of min ||A X - B||; A, B untouched."""
     m, n = A.shape
@@ -75,10 +83,7 @@ def lstsq(A, Bm, opts=None, X=None, work=None, info=None):
     if X is None:
         X = torch.empty((nrhs, n), dtype=torch.float64, device=A.device).t()
     if work is None:
-        nbytes = B.tqr_lstsq_work_size(m, n, nrhs, opts)
-        if nbytes == 0:
-            raise B.TqrError("invalid shape/options for lstsq")
-        work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+        work = lstsq_workspace(m, n, nrhs, opts, A.device)
     B.tqr_lstsq(m, n, nrhs, A.data_ptr(), _ld(A), Bm.data_ptr(), _ld(Bm), X.data_ptr(), _ld(X),
                 work.data_ptr(), work.numel(), opts, None if info is None else info.data_ptr(), _stream())
     return X

@@ -33,7 +33,10 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-enum PlanKind { PK_FACTOR = 0, PK_APPLY = 1, PK_SOLVE = 2 };
+// Plans: factor only; Q^T B only; R X = B only; and the whole least-squares
+// solve in one graph (factor, Q^T B and R X = B with the right-hand sides as
+// extra tile columns, so B's updates overlap the factorization).
+enum PlanKind { PK_FACTOR = 0, PK_APPLY = 1, PK_SOLVE = 2, PK_LSTSQ = 3 };
 
 struct PlanKey {
   int kind, p, q, nbcols, family, tree, param, stripes, stripes_b, priority;
@@ -62,6 +65,9 @@ std::map<int, int> g_grid;
 std::map<std::pair<int, int>, int64_t> g_spin;
 int64_t *g_trace = nullptr;
 int64_t g_trace_cap = 0;
+// executor launch timing (diagnostics): one event pair per launch
+bool g_timing = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
 
 std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
   {
@@ -77,9 +83,9 @@ std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
   spec.stripes = k.stripes;
   spec.nbcols = k.nbcols;
   spec.stripes_b = k.stripes_b;
-  spec.panels = (k.kind == PK_FACTOR);
-  spec.b_updates = (k.kind == PK_APPLY);
-  spec.solve = (k.kind == PK_SOLVE);
+  spec.panels = (k.kind == PK_FACTOR || k.kind == PK_LSTSQ);
+  spec.b_updates = (k.kind == PK_APPLY || k.kind == PK_LSTSQ);
+  spec.solve = (k.kind == PK_SOLVE || k.kind == PK_LSTSQ);
   std::vector<Elim> list;
   if (k.kind != PK_SOLVE) list = make_list(k.tree, k.p, k.q, k.param);
   hp->g = build_graph(list, spec);
@@ -183,7 +189,8 @@ int resolve(const tqr_opts *o, Resolved *r) {
   return TQR_OK;
 }
 
-PlanKey make_key(int kind, int p, int q, int nbcols, const Resolved &r) {
+PlanKey make_key(int kind, int p, int q, int64_t nrhs, const Resolved &r) {
+  const int nbcols = (kind == PK_FACTOR) ? 0 : (int)cdiv(nrhs, r.nb);
   PlanKey k{};
   k.kind = kind;
   k.p = p;
@@ -193,7 +200,8 @@ PlanKey make_key(int kind, int p, int q, int nbcols, const Resolved &r) {
   k.tree = (kind == PK_SOLVE) ? 0 : r.tree;
   k.param = (kind == PK_SOLVE) ? 0 : r.param;
   k.stripes = r.stripes;
-  k.stripes_b = (kind == PK_FACTOR) ? 1 : r.stripes;
+  // right-hand sides narrower than one stripe get one task per tile
+  k.stripes_b = (kind == PK_FACTOR || nrhs <= r.nb / r.stripes) ? 1 : r.stripes;
   k.priority = r.priority;
   if (kind == PK_SOLVE) k.family = 0;
   return k;
@@ -213,8 +221,7 @@ int run_plan(int kind, int64_t m, int64_t n, double *A, int64_t lda, double *B, 
              hipStream_t stream) {
   const int nb = r.nb;
   const int64_t p = cdiv(m, nb), q = cdiv(n, nb);
-  const int nbcols = (kind == PK_FACTOR) ? 0 : (int)cdiv(nrhs, nb);
-  const PlanKey key = make_key(kind, (int)p, (int)q, nbcols, r);
+  const PlanKey key = make_key(kind, (int)p, (int)q, kind == PK_FACTOR ? 0 : nrhs, r);
   auto hp = host_plan(key);
   if (!hp->valid) return TQR_E_INTERNAL;
   const size_t tf = tfactor_bytes(p, q, nb, r.ib);
@@ -251,21 +258,30 @@ int run_plan(int kind, int64_t m, int64_t n, double *A, int64_t lda, double *B, 
   a.q = (int)q;
   a.nb = nb;
   a.ib = r.ib;
-  a.sw = nb / (kind == PK_FACTOR ? key.stripes : key.stripes_b);
+  a.sw = nb / key.stripes;
+  a.sw_b = nb / key.stripes_b;
   a.dma_ok = ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda % 2) == 0) ? 1 : 0;
   a.spin_limit = spin_limit_ticks(dev);
   a.trace = g_trace;
   a.trace_cap = g_trace_cap;
   const int grid = grid_size(dev, nb, r.ib);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (g_timing && hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess) {
+    hipEventRecord(ev0, stream);
+  }
   hipError_t e = launch_exec(a, r.exec == TQR_EXEC_SEQUENTIAL ? 1 : 0, grid, hp->g.order.data(),
                              info, stream);
+  if (ev1) {
+    hipEventRecord(ev1, stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_events.emplace_back(ev0, ev1);
+  }
   return e == hipSuccess ? TQR_OK : TQR_E_HIP;
 }
 
 int64_t plan_tasks(int kind, int64_t m, int64_t n, int64_t nrhs, const Resolved &r) {
   const int64_t p = cdiv(m, r.nb), q = cdiv(n, r.nb);
-  const int nbcols = (kind == PK_FACTOR) ? 0 : (int)cdiv(nrhs, r.nb);
-  return (int64_t)host_plan(make_key(kind, (int)p, (int)q, nbcols, r))->g.tasks.size();
+  return (int64_t)host_plan(make_key(kind, (int)p, (int)q, kind == PK_FACTOR ? 0 : nrhs, r))->g.tasks.size();
 }
 
 }  // namespace
@@ -367,7 +383,7 @@ size_t tqr_lstsq_work_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o
   Resolved r;
   if (resolve(o, &r)) return 0;
   size_t t = tqr_workspace_size(m, n, nrhs, o);
-  const int64_t nt = plan_tasks(PK_SOLVE, m, n, nrhs, r);
+  const int64_t nt = plan_tasks(PK_LSTSQ, m, n, nrhs, r);
   t = std::max(t, kHeader + align_up(tfactor_bytes(cdiv(m, r.nb), cdiv(n, r.nb), r.nb, r.ib)) +
                       state_bytes(nt));
   return align_up((size_t)m * n * 8) + align_up((size_t)m * nrhs * 8) + t;
@@ -400,11 +416,7 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
     return TQR_E_HIP;
   if (hipMemcpy2DAsync(Bc, m * 8, B, ldb * 8, m * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return TQR_E_HIP;
-  rc = run_plan(PK_FACTOR, m, n, Ac, m, nullptr, 0, 0, T, tb, r, info, stream);
-  if (rc) return rc;
-  rc = run_plan(PK_APPLY, m, n, Ac, m, Bc, m, nrhs, T, tb, r, info, stream);
-  if (rc) return rc;
-  rc = run_plan(PK_SOLVE, m, n, Ac, m, Bc, m, nrhs, T, tb, r, info, stream);
+  rc = run_plan(PK_LSTSQ, m, n, Ac, m, Bc, m, nrhs, T, tb, r, info, stream);
   if (rc) return rc;
   if (hipMemcpy2DAsync(X, ldx * 8, Bc, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return TQR_E_HIP;
@@ -458,6 +470,30 @@ int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, in
   return hp->valid ? TQR_OK : TQR_E_INTERNAL;
 }
 
+void tqr_debug_timing(int32_t enable) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto &pr : g_events) {
+    hipEventDestroy(pr.first);
+    hipEventDestroy(pr.second);
+  }
+  g_events.clear();
+  g_timing = enable != 0;
+}
+
+int tqr_debug_timing_read(double *ms_total, int64_t *launches) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  double tot = 0.0;
+  for (auto &pr : g_events) {
+    if (hipEventSynchronize(pr.second) != hipSuccess) return TQR_E_HIP;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess) return TQR_E_HIP;
+    tot += ms;
+  }
+  if (ms_total) *ms_total = tot;
+  if (launches) *launches = (int64_t)g_events.size();
+  return TQR_OK;
+}
+
 void tqr_debug_trace(int64_t *buf, int64_t cap) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_trace = buf;
@@ -467,11 +503,11 @@ void tqr_debug_trace(int64_t *buf, int64_t cap) {
 int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *tasks,
                     int64_t cap) {
   if (m < 1 || n < 1 || n > m) return -1;
+  if (kind < PK_FACTOR || kind > PK_LSTSQ) return -4;
   Resolved r;
   int rc = resolve(o, &r);
   if (rc) return rc;
-  const int nbcols = (kind == PK_FACTOR) ? 0 : (int)cdiv(nrhs, r.nb);
-  auto hp = host_plan(make_key(kind, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), nbcols, r));
+  auto hp = host_plan(make_key(kind, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), kind == PK_FACTOR ? 0 : nrhs, r));
   const int64_t nt = (int64_t)hp->g.tasks.size();
   if (tasks && cap >= nt)
     for (int64_t t = 0; t < nt; t++) {

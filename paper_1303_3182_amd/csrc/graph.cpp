@@ -52,7 +52,7 @@ class Builder {
   // Kernels that the first column needs before any elimination (TT only:
   // algorithm alg.elimTR with k = 0 triangularises every tile of column 1).
   void start() {
-    if (spec_.solve) return;
+    if (solve_only()) return;
     if (spec_.family == FAM_TT)
       for (int i = 0; i < p_; i++) factor_row(i, 0);
   }
@@ -72,7 +72,7 @@ class Builder {
   }
 
   void end() {
-    if (spec_.solve) return;
+    if (solve_only()) return;
     // The last diagonal tile of a square tile matrix is never a pivot in
     // the hybrid family; it still has to be triangularised.
     if (spec_.family == FAM_HYBRID && p_ == q_ && !tri_[idx(q_ - 1, q_ - 1)])
@@ -80,19 +80,26 @@ class Builder {
   }
 
   // Back-substitution R X = B over the tile columns of B: for k = q-1..0,
-  // X(k) = R(k,k)^{-1} B(k), then B(i) -= R(i,k) X(k) for i < k.
+  // X(k) = R(k,k)^{-1} B(k), then B(i) -= R(i,k) X(k) for i < k.  R(k,k)
+  // is the triangle item of tile (k,k); R(i,k), i < k, is the last state of
+  // the update target tile (i,k) (every stripe), so after a factorization
+  // in the same graph these tasks wait for exactly the kernels that
+  // finish those tiles.
   void solve() {
     for (int jb = 0; jb < spec_.nbcols; jb++)
       for (int s = 0; s < spec_.stripes_b; s++)
         for (int k = q_ - 1; k >= 0; k--) {
           emit(K_TRSM, k, k, k, q_ + jb, s, {&u_[idx(k, k)]}, {xitem(k, q_ + jb, s)});
-          for (int i = k - 1; i >= 0; i--)
-            emit(K_GEMM, i, i, k, q_ + jb, s, {&u_[idx(i, k)], xitem(k, q_ + jb, s)},
-                 {xitem(i, q_ + jb, s)});
+          for (int i = k - 1; i >= 0; i--) {
+            std::vector<ItemState *> rd = {xitem(k, q_ + jb, s)};
+            for (int sa = 0; sa < spec_.stripes; sa++) rd.push_back(xitem(i, k, sa));
+            emit(K_GEMM, i, i, k, q_ + jb, s, rd, {xitem(i, q_ + jb, s)});
+          }
         }
   }
 
  private:
+  bool solve_only() const { return spec_.solve && !spec_.panels && !spec_.b_updates; }
   size_t idx(int i, int k) const { return (size_t)i * q_ + k; }
   ItemState *xitem(int i, int j, int s) { return &x_[((size_t)i * qt_ + j) * smax_ + s]; }
   int stripes_of(int j) const { return j < q_ ? spec_.stripes : spec_.stripes_b; }
@@ -354,13 +361,12 @@ std::vector<Elim> make_list(int tree, int p, int q, int param) {
 Graph build_graph(const std::vector<Elim> &list, const GraphSpec &spec, std::vector<double> *zero_t,
                   std::vector<double> *geqrt_t) {
   Builder b(spec, true);
-  if (spec.solve) {
-    b.solve();
-  } else {
+  if (spec.panels || spec.b_updates) {
     b.start();
     for (const Elim &e : list) b.elim(e);
     b.end();
   }
+  if (spec.solve) b.solve();
   if (zero_t) *zero_t = b.zero_times();
   if (geqrt_t) *geqrt_t = b.geqrt_times();
   return std::move(b.graph());

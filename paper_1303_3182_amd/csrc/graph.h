@@ -47,7 +47,7 @@ struct GraphSpec {
   int stripes_b = 1;     // update tasks per target tile of B
   bool panels = true;    // emit the factor kernels (and A-column updates)
   bool b_updates = false;  // emit updates of the B columns
-  bool solve = false;    // emit only the back-substitution R X = B
+  bool solve = false;    // emit the back-substitution R X = B (after the above)
 };
 
 struct Graph {

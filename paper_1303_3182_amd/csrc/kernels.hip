@@ -96,7 +96,9 @@ struct Smem {
   static constexpr int LDW = WC + 16;  // YL row stride
   // reflectors of one block, two buffers: VL[buf][cc*LDV + r].  The solve
   // kernels use VL[1] as YL (a block row of X, YL[kk*LDW + n]).
-  static constexpr int VSZ = (IB * LDV > IB * LDW) ? IB * LDV : IB * LDW;
+  static constexpr int VS1 = (IB * LDV > IB * LDW) ? IB * LDV : IB * LDW;
+  static constexpr int VS2 = (NB < 64 ? NB : 64) * NB / 2;  // half a column block of R (solve)
+  static constexpr int VSZ = VS1 > VS2 ? VS1 : VS2;
   double VL[2][VSZ];
   double TL[2][IB * LDT];              // T of one block: TL[buf][cc*LDT + r] = T(r,cc)
   double vbuf[2][NB + IB];             // panel: current reflector (zero past the panel)
@@ -737,6 +739,91 @@ __device__ __forceinline__ void trsm_tile(const double *R, int64_t ldr, int nk, 
       }
 }
 
+// Broadcast of lane l's double (l wave-uniform).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, l);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Back-substitution R x = y for a few right-hand sides: one wave per
+// column (two at most), each lane holding rows lane, lane + 64, ... in
+// registers.  R's columns are staged in LDS 64 at a time (all rows above
+// them).  Row r, from the bottom, is finished by its owner lane and
+// broadcast with a lane read; every lane then removes its contribution from
+// the rows above.  A chain of nk short steps, instead of the blocked
+// solve's serial per-column loops.
+template <int NB, int IB, int WC>
+__device__ __forceinline__ void trsm_waves(const double *R, int64_t ldr, int nk, double *X, int64_t ldx,
+                                           int ncols, int row0, int32_t *singular, Smem<NB, IB, WC> &sm) {
+  constexpr int U = (NB + 63) / 64;  // row groups of 64
+  constexpr int CB = NB < 64 ? NB : 64;
+  constexpr int CPW = 2;             // columns per wave
+  static_assert(2 * Smem<NB, IB, WC>::VSZ >= CB * NB, "LDS too small for a column block of R");
+  double *Ls = &sm.VL[0][0];         // VL[0] and VL[1] are contiguous
+  const int tid = opaque_tid();
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  double y[CPW][U];
+#pragma unroll
+  for (int c = 0; c < CPW; c++) {
+    const int n = min(w + (NT / 64) * c, ncols - 1);
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int row = u * 64 + lane;
+      y[c][u] = zmask(X[n * ldx + min(row, nk - 1)], row < nk);
+    }
+  }
+#pragma unroll
+  for (int ub = U - 1; ub >= 0; ub--) {
+    const int c0 = ub * CB;
+    if (c0 >= nk) continue;
+    const int c1 = min(nk, c0 + CB);
+    __syncthreads();  // the previous block's readers are done
+    for (int idx = tid; idx < (c1 - c0) * c1; idx += NT) {
+      const int cc = idx / c1, row = idx % c1;
+      Ls[cc * NB + row] = R[(c0 + cc) * ldr + row];
+    }
+    __syncthreads();
+    double uc[U], un[U];
+    auto load_col = [&](int l, double *dst) {
+      const int lc = max(l, 0);
+#pragma unroll
+      for (int u = 0; u <= ub; u++) dst[u] = Ls[lc * NB + min(u * 64 + lane, c1 - 1)];
+    };
+    load_col(c1 - 1 - c0, uc);
+    for (int l = c1 - 1 - c0; l >= 0; l--) {
+      const int r = c0 + l;
+      load_col(l - 1, un);
+      const double d = Ls[l * NB + r];
+      if (d == 0.0 && w == 0 && lane == 0) atomicMin(singular, row0 + r + 1);
+#pragma unroll
+      for (int c = 0; c < CPW; c++) {
+        const double xr = readlane_d(y[c][ub], l) / d;
+#pragma unroll
+        for (int u = 0; u <= ub; u++) {
+          if (u < ub)
+            y[c][u] = fma(-uc[u], xr, y[c][u]);
+          else
+            y[c][u] = (lane < l) ? fma(-uc[u], xr, y[c][u]) : ((lane == l) ? xr : y[c][u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u <= ub; u++) uc[u] = un[u];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPW; c++) {
+    const int n = w + (NT / 64) * c;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int row = u * 64 + lane;
+      if (n < ncols && row < nk) X[n * ldx + row] = y[c][u];
+    }
+  }
+}
+
 // ================================================================== tasks
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
@@ -767,12 +854,15 @@ __device__ __forceinline__ void run_task(const ExecArgs &a, const Task &t, Smem<
     const int jb = t.j - a.q;
     const int nkk = (int)min((int64_t)NB, a.n - (int64_t)t.k * NB);
     const int ncols = (int)min((int64_t)NB, a.nrhs - (int64_t)jb * NB);
-    const int cbeg = t.stripe * a.sw;
-    const int cend = imin(ncols, cbeg + a.sw);
+    const int cbeg = t.stripe * a.sw_b;
+    const int cend = imin(ncols, cbeg + a.sw_b);
     double *Bc = a.B + (int64_t)jb * NB * a.ldb;
     for (int cs = cbeg; cs < cend; cs += WC) {
       const int nc = imin(WC, cend - cs);
-      if (kind == K_TRSM)
+      if (kind == K_TRSM && nc <= 2 * (NT / 64))
+        trsm_waves<NB, IB, WC>(tileA(t.k, t.k), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
+                               a.ldb, nc, t.k * NB, &a.ctl->pad[0], sm);
+      else if (kind == K_TRSM)
         trsm_tile<NB, IB, WC>(tileA(t.k, t.k), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
                               a.ldb, nc, t.k * NB, &a.ctl->pad[0], sm);
       else
@@ -797,8 +887,9 @@ __device__ __forceinline__ void run_task(const ExecArgs &a, const Task &t, Smem<
   const double *V = tileA(t.i, t.k);
   const int vrows = rowsOf(t.i);
   const int vcols = (int)min((int64_t)NB, a.n - (int64_t)t.k * NB);
-  const int cbeg = t.stripe * a.sw;
-  const int cend = imin(ncols, cbeg + a.sw);
+  const int sw = (t.j < a.q) ? a.sw : a.sw_b;
+  const int cbeg = t.stripe * sw;
+  const int cend = imin(ncols, cbeg + sw);
   const bool dma = a.dma_ok && NB >= 128 && vrows == NB && vcols == NB;
   for (int cs = cbeg; cs < cend; cs += CHUNK) {
     const int nc = imin(CHUNK, cend - cs);

@@ -59,8 +59,10 @@ struct ExecArgs {
   int64_t ldb, nrhs;
   double *Tf;       // T factors: ((i*q + k)*2 + which) * ib * nb doubles
   int32_t p, q, nb, ib;
-  int32_t sw;       // stripe width (columns per update task)
+  int32_t sw;       // stripe width of updates of A's columns (columns per task)
+  int32_t sw_b;     // stripe width of tasks on B's columns
   int32_t dma_ok;   // A is 16-byte aligned with even lda: tiles may be DMA'd to LDS
+  int32_t pad_;
   int64_t spin_limit;  // watchdog, in wall-clock ticks
   int64_t *trace;      // optional: per task {start, end, workgroup, xcc}
   int64_t trace_cap;   // tasks that fit in `trace`

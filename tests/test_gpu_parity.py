@@ -105,11 +105,14 @@ def test_stripes_do_not_change_results(stripes):
 
 @pytest.mark.parametrize("kernels", ["tt", "hybrid"])
 def test_apply_qt_and_lstsq(kernels):
-    for (m, n, nb, nrhs) in [(512, 256, 128, 1), (1000, 333, 64, 5), (700, 700, 128, 3), (4096, 300, 256, 2)]:
+    # nrhs <= 8 takes the one-wave-per-column back-substitution, larger
+    # counts the blocked one
+    for (m, n, nb, nrhs) in [(512, 256, 128, 1), (1000, 333, 64, 5), (700, 700, 128, 3), (4096, 300, 256, 2),
+                             (600, 200, 64, 40), (300, 100, 32, 7), (520, 260, 256, 9)]:
         case("apply/lstsq %s m=%d n=%d nb=%d nrhs=%d" % (kernels, m, n, nb, nrhs))
         A0 = synth.gaussian(m, n, 11 + m)
         B0 = synth.gaussian_rhs(m, nrhs, 11 + m)
-        o = T.default_opts(nb=nb, tree="grasap", kernels=kernels)
+        o = T.default_opts(nb=nb, ib=16 if nb == 32 else 32, tree="grasap", kernels=kernels)
         A, W = _factor(A0, o)
         Bm = T.colmajor(B0)
         T.apply_qt(A, W, Bm, o)
@@ -130,6 +133,11 @@ def test_apply_qt_and_lstsq(kernels):
             xo = H.back_substitute(Ro, QtBo[:n, c])
             kap = np.linalg.cond(A0)
             assert np.linalg.norm(x - xo) <= 100 * kap ** 2 * EPS * np.linalg.norm(xo) + 1e-300
+        # the fused least-squares graph runs the same kernels in the same
+        # per-tile order as factor + apply_qt + solve_r: identical bits
+        T.solve_r(A, W, Bm, o)
+        torch.cuda.synchronize()
+        assert np.array_equal(Bm.cpu().numpy()[:n], X.cpu().numpy())
 
 
 def test_edge_cases():

@@ -82,3 +82,25 @@ def test_header_symbols_exported():
     L = ctypes.CDLL(T.library_path())
     for nm in sorted(names):
         assert hasattr(L, nm), nm
+
+
+def test_fused_least_squares_graph():
+    """The least-squares graph (kind 3) holds exactly the factor, Q^T B and
+    R X = B tasks: counts add up; with one right-hand-side column the B
+    updates are one per factor kernel (UNMQR per GEQRT, TTMQR per TTQRT),
+    and the solve has q TRSM and q(q-1)/2 GEMM tasks."""
+    for (m, n, nb, nrhs) in [(512, 256, 128, 1), (1000, 333, 64, 5), (16384, 2048, 256, 1), (700, 700, 128, 130)]:
+        o = T.default_opts(nb=nb, tree="grasap")
+        f = T.debug_graph(m, n, o, 0, 0)
+        a = T.debug_graph(m, n, o, nrhs, 1)
+        s = T.debug_graph(m, n, o, nrhs, 2)
+        ls = T.debug_graph(m, n, o, nrhs, 3)
+        assert len(ls) == len(f) + len(a) + len(s)
+        kinds = [t[0] for t in ls]
+        q = -(-n // nb)
+        fk = [t[0] for t in f]
+        if nrhs == 1:
+            assert kinds.count(6) == q and kinds.count(7) == q * (q - 1) // 2
+            assert kinds.count(3) == fk.count(3) + fk.count(0)
+            assert kinds.count(5) == fk.count(5) + fk.count(2)
+        assert ls[0][7] == 0
