@@ -153,6 +153,25 @@ int tqr_solve_r(int64_t m, int64_t n, const double *A, int64_t lda, void *T, siz
  * against the caller's A (at most opts.max_refine steps); info then
  * reports TQR_INFO_NOCONV if the tolerance was not reached. */
 size_t tqr_lstsq_work_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o);
+
+/* Refinement report, at offset 0 of tqr_lstsq's `work` (device memory,
+ * valid once the stream has passed the call).  With update_dtype TQR_F64
+ * only `done` = 0 and `iterations` = 0 are written.  Refinement (project
+ * addition; the thesis treats FP64 only): square systems take classical
+ * iterative refinement, x += R^{-1} (Q^T r)(1:n); rectangular ones
+ * refinement of the semi-normal equations, x += R^{-1} R^{-T} A^T r; the
+ * residuals r = b - A x and A^T r are FP64 with compensated dot products.
+ * Each iteration first tests the backward error of the current x
+ * (square: ||r|| / (||A||_F ||x|| + ||b||); rectangular:
+ * ||A^T r|| / (||A||_F ||r||)) against opts.refine_tol (0: 16 * 2^-52),
+ * worst over the right-hand sides, and stops when it is met. */
+#define TQR_REFINE_HISTORY 24
+typedef struct tqr_refine_report {
+  int32_t done;           /* 1: the tolerance was met                          */
+  int32_t iterations;     /* corrections applied before the last test          */
+  double backward_error;  /* measured at the last test (-1: none)              */
+  double history[TQR_REFINE_HISTORY]; /* at each test (-1: not reached)       */
+} tqr_refine_report;
 int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
               int64_t ldb, double *X, int64_t ldx, void *work, size_t work_bytes,
               const tqr_opts *o, int32_t *info, hipStream_t stream);
@@ -208,9 +227,11 @@ int tqr_debug_timing_read(double *ms_total, int64_t *launches);
 int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o,
                     int32_t *tasks, int64_t cap);
 
-/* Debug only: successor lists (CSR) of the factor plan; off has ntasks+1
- * entries, succ cap entries.  Returns the number of edges or -1. */
-int tqr_debug_succ(int64_t m, int64_t n, const tqr_opts *o, int32_t *off, int32_t *succ, int64_t cap);
+/* Debug only: successor lists (CSR) of a plan (kind and nrhs as for
+ * tqr_debug_graph); off has ntasks+1 entries, succ cap entries.  Returns the
+ * number of edges, or a negative value (bad arguments, cap too small). */
+int tqr_debug_succ(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *off,
+                   int32_t *succ, int64_t cap);
 
 #ifdef __cplusplus
 }

@@ -61,7 +61,7 @@ def lib():
             "tqr_debug_timing": (None, [i32]),
             "tqr_debug_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), i64p]),
             "tqr_debug_graph": (ctypes.c_int, [i64, i64, i64, i32, op, i32p, i64]),
-            "tqr_debug_succ": (ctypes.c_int, [i64, i64, op, i32p, i32p, i64]),
+            "tqr_debug_succ": (ctypes.c_int, [i64, i64, i64, i32, op, i32p, i32p, i64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -69,6 +69,9 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+REFINE_HISTORY = 24  # TQR_REFINE_HISTORY
 
 
 def _check(rc, what):
@@ -195,11 +198,12 @@ def debug_graph(m, n, opts=None, nrhs=0, kind=0):
     return [tuple(buf[8 * t:8 * t + 8]) for t in range(nt)]
 
 
-def debug_succ(m, n, opts=None):
+def debug_succ(m, n, opts=None, nrhs=0, kind=0):
+    """Successor lists (CSR offsets, successors) of a plan."""
     L = lib()
-    tasks = debug_graph(m, n, opts)
+    tasks = debug_graph(m, n, opts, nrhs, kind)
     ne = sum(t[6] for t in tasks)
     off = (ctypes.c_int32 * (len(tasks) + 1))()
     succ = (ctypes.c_int32 * max(ne, 1))()
-    L.tqr_debug_succ(m, n, _opts_ptr(opts), off, succ, ne)
+    L.tqr_debug_succ(m, n, nrhs, kind, _opts_ptr(opts), off, succ, ne)
     return list(off), list(succ)

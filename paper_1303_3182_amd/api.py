@@ -87,3 +87,14 @@ def lstsq(A, Bm, opts=None, X=None, work=None, info=None):
     B.tqr_lstsq(m, n, nrhs, A.data_ptr(), _ld(A), Bm.data_ptr(), _ld(Bm), X.data_ptr(), _ld(X),
                 work.data_ptr(), work.numel(), opts, None if info is None else info.data_ptr(), _stream())
     return X
+
+
+def refine_report(work):
+    """The refinement report that tqr_lstsq leaves at the start of its
+    workspace: dict(done, iterations, backward_error, history)."""
+    import numpy as np
+    raw = work[:8 + 8 + 8 * B.REFINE_HISTORY].cpu().numpy().tobytes()
+    done, iters = np.frombuffer(raw[:8], dtype=np.int32)
+    vals = np.frombuffer(raw[8:], dtype=np.float64)
+    hist = [float(v) for v in vals[1:] if v >= 0.0]
+    return {"done": int(done), "iterations": int(iters), "backward_error": float(vals[0]), "history": hist}

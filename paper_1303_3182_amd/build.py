@@ -18,8 +18,12 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + CSRC, "-I" + INCLUDE, "-I/opt/roc
 # MFMA accumulators in VGPRs: avoids AGPR<->VGPR copies around guarded MFMA blocks.
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-ffp-contract=fast", "-mllvm", "-amdgpu-mfma-vgpr-form"]
-HOST_SOURCES = ["graph.cpp", "api.cpp"]
+HOST_SOURCES = ["graph.cpp", "api.cpp", "configs.cpp"]
 DEVICE_SOURCES = ["kernels.hip"]
+SHARED_DEVICE_SOURCES = ["refine.hip"]  # compiled once
+# (nb, ib) tile configurations; kernels.hip is compiled once per entry
+# (the list must match TQR_CONFIGS in configs.cpp).
+CONFIGS = [(32, 16), (64, 16), (64, 32), (128, 32), (256, 32)]
 
 
 def _run(cmd):
@@ -30,7 +34,7 @@ def _run(cmd):
     return r
 
 
-def build(verbose=False, jobs=4):
+def build(verbose=False, jobs=8):
     """Compile every source and link libtqr.so in the package directory."""
     os.makedirs(BUILD, exist_ok=True)
     procs, objs = [], []
@@ -40,6 +44,12 @@ def build(verbose=False, jobs=4):
         procs.append([HIPCC, "-x", "c++", "-c", os.path.join(CSRC, src), "-o", obj] + COMMON +
                      ["-D__HIP_PLATFORM_AMD__"])
     for src in DEVICE_SOURCES:
+        for nb, ib in CONFIGS:
+            obj = os.path.join(BUILD, "%s.%d_%d.o" % (src, nb, ib))
+            objs.append(obj)
+            procs.append([HIPCC, "-c", os.path.join(CSRC, src), "-o", obj, "-DTQR_CFG_NB=%d" % nb,
+                          "-DTQR_CFG_IB=%d" % ib] + COMMON + DEVICE)
+    for src in SHARED_DEVICE_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)
         procs.append([HIPCC, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + DEVICE)

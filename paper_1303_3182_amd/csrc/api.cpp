@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "graph.h"
+#include "refine.h"
 #include "tqr.h"
 #include "tqr_types.h"
 
@@ -36,7 +37,8 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Plans: factor only; Q^T B only; R X = B only; and the whole least-squares
 // solve in one graph (factor, Q^T B and R X = B with the right-hand sides as
 // extra tile columns, so B's updates overlap the factorization).
-enum PlanKind { PK_FACTOR = 0, PK_APPLY = 1, PK_SOLVE = 2, PK_LSTSQ = 3 };
+enum PlanKind { PK_FACTOR = 0, PK_APPLY = 1, PK_SOLVE = 2, PK_LSTSQ = 3, PK_SOLVET = 4 };
+bool solve_kind(int k) { return k == PK_SOLVE || k == PK_SOLVET; }
 
 struct PlanKey {
   int kind, p, q, nbcols, family, tree, param, stripes, stripes_b, priority;
@@ -86,8 +88,9 @@ std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
   spec.panels = (k.kind == PK_FACTOR || k.kind == PK_LSTSQ);
   spec.b_updates = (k.kind == PK_APPLY || k.kind == PK_LSTSQ);
   spec.solve = (k.kind == PK_SOLVE || k.kind == PK_LSTSQ);
+  spec.solve_t = (k.kind == PK_SOLVET);
   std::vector<Elim> list;
-  if (k.kind != PK_SOLVE) list = make_list(k.tree, k.p, k.q, k.param);
+  if (!solve_kind(k.kind)) list = make_list(k.tree, k.p, k.q, k.param);
   hp->g = build_graph(list, spec);
   finalize(hp->g, k.priority != 0);
   hp->valid = validate(hp->g);
@@ -157,7 +160,8 @@ int64_t spin_limit_ticks(int dev) {
 }
 
 struct Resolved {
-  int nb, ib, tree, param, family, stripes, priority, exec;
+  int nb, ib, tree, param, family, stripes, priority, exec, update_dtype, max_refine;
+  double refine_tol;
 };
 
 int resolve(const tqr_opts *o, Resolved *r) {
@@ -179,7 +183,11 @@ int resolve(const tqr_opts *o, Resolved *r) {
   if (r->tree < TQR_FLAT || r->tree > TQR_ASAP) return TQR_E_UNSUPPORTED;
   if (r->family != TQR_TT && r->family != TQR_HYBRID) return TQR_E_UNSUPPORTED;
   if (r->exec != TQR_EXEC_PERSISTENT && r->exec != TQR_EXEC_SEQUENTIAL) return TQR_E_UNSUPPORTED;
-  if (x.update_dtype != TQR_F64) return TQR_E_UNSUPPORTED;
+  if (x.update_dtype != TQR_F64 && x.update_dtype != TQR_F32 && x.update_dtype != TQR_BF16)
+    return TQR_E_UNSUPPORTED;
+  r->update_dtype = x.update_dtype;
+  r->max_refine = x.max_refine < 0 ? 0 : x.max_refine;
+  r->refine_tol = x.refine_tol;
   const int wc = chunk_width(r->nb, r->ib);
   int s = x.stripes;
   if (s <= 0) s = std::max(1, r->nb / std::max(wc, 64));
@@ -197,13 +205,13 @@ PlanKey make_key(int kind, int p, int q, int64_t nrhs, const Resolved &r) {
   k.q = q;
   k.nbcols = nbcols;
   k.family = r.family;
-  k.tree = (kind == PK_SOLVE) ? 0 : r.tree;
-  k.param = (kind == PK_SOLVE) ? 0 : r.param;
+  k.tree = solve_kind(kind) ? 0 : r.tree;
+  k.param = solve_kind(kind) ? 0 : r.param;
   k.stripes = r.stripes;
   // right-hand sides narrower than one stripe get one task per tile
   k.stripes_b = (kind == PK_FACTOR || nrhs <= r.nb / r.stripes) ? 1 : r.stripes;
   k.priority = r.priority;
-  if (kind == PK_SOLVE) k.family = 0;
+  if (solve_kind(kind)) k.family = 0;
   return k;
 }
 
@@ -218,7 +226,7 @@ size_t state_bytes(int64_t ntasks) {
 // Runs one plan on the device.
 int run_plan(int kind, int64_t m, int64_t n, double *A, int64_t lda, double *B, int64_t ldb,
              int64_t nrhs, void *T, size_t t_bytes, const Resolved &r, int32_t *info,
-             hipStream_t stream) {
+             hipStream_t stream, const int32_t *skip = nullptr) {
   const int nb = r.nb;
   const int64_t p = cdiv(m, nb), q = cdiv(n, nb);
   const PlanKey key = make_key(kind, (int)p, (int)q, kind == PK_FACTOR ? 0 : nrhs, r);
@@ -261,6 +269,8 @@ int run_plan(int kind, int64_t m, int64_t n, double *A, int64_t lda, double *B, 
   a.sw = nb / key.stripes;
   a.sw_b = nb / key.stripes_b;
   a.dma_ok = ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda % 2) == 0) ? 1 : 0;
+  a.update_dtype = r.update_dtype;
+  a.skip = skip;
   a.spin_limit = spin_limit_ticks(dev);
   a.trace = g_trace;
   a.trace_cap = g_trace_cap;
@@ -282,6 +292,48 @@ int run_plan(int kind, int64_t m, int64_t n, double *A, int64_t lda, double *B, 
 int64_t plan_tasks(int kind, int64_t m, int64_t n, int64_t nrhs, const Resolved &r) {
   const int64_t p = cdiv(m, r.nb), q = cdiv(n, r.nb);
   return (int64_t)host_plan(make_key(kind, (int)p, (int)q, kind == PK_FACTOR ? 0 : nrhs, r))->g.tasks.size();
+}
+
+// tqr_lstsq's workspace, in order: the refinement report, copies of A and
+// B, the factor workspace (T factors and executor state for the largest
+// plan), and, with low-precision updates, the refinement buffers: X, the
+// residual R (m x nrhs), A^T R (n x nrhs) and the residual partial sums.
+struct LsLayout {
+  size_t report, ac, bc, t, t_bytes, xw, rw, sw, part, total;
+};
+
+LsLayout ls_layout(int64_t m, int64_t n, int64_t nrhs, const Resolved &r) {
+  LsLayout L{};
+  int64_t nt = plan_tasks(PK_LSTSQ, m, n, nrhs, r);
+  nt = std::max(nt, plan_tasks(PK_FACTOR, m, n, 0, r));
+  const bool mixed = r.update_dtype != TQR_F64;
+  if (mixed) {
+    nt = std::max(nt, plan_tasks(PK_APPLY, m, n, nrhs, r));
+    nt = std::max(nt, plan_tasks(PK_SOLVE, m, n, nrhs, r));
+    nt = std::max(nt, plan_tasks(PK_SOLVET, m, n, nrhs, r));
+  }
+  size_t off = 0;
+  L.report = off;
+  off += align_up(sizeof(tqr_refine_report));
+  L.ac = off;
+  off += align_up((size_t)m * n * 8);
+  L.bc = off;
+  off += align_up((size_t)m * nrhs * 8);
+  L.t = off;
+  L.t_bytes = kHeader + align_up(tfactor_bytes(cdiv(m, r.nb), cdiv(n, r.nb), r.nb, r.ib)) + state_bytes(nt);
+  off += align_up(L.t_bytes);
+  if (mixed) {
+    L.xw = off;
+    off += align_up((size_t)n * nrhs * 8);
+    L.rw = off;
+    off += align_up((size_t)m * nrhs * 8);
+    L.sw = off;
+    off += align_up((size_t)n * nrhs * 8);
+    L.part = off;
+    off += align_up(refine_partial_bytes(m, n, nrhs));
+  }
+  L.total = off;
+  return L;
 }
 
 }  // namespace
@@ -382,11 +434,7 @@ size_t tqr_lstsq_work_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o
   if (m < 1 || n < 1 || n > m || nrhs < 1) return 0;
   Resolved r;
   if (resolve(o, &r)) return 0;
-  size_t t = tqr_workspace_size(m, n, nrhs, o);
-  const int64_t nt = plan_tasks(PK_LSTSQ, m, n, nrhs, r);
-  t = std::max(t, kHeader + align_up(tfactor_bytes(cdiv(m, r.nb), cdiv(n, r.nb), r.nb, r.ib)) +
-                      state_bytes(nt));
-  return align_up((size_t)m * n * 8) + align_up((size_t)m * nrhs * 8) + t;
+  return ls_layout(m, n, nrhs, r).total;
 }
 
 int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
@@ -405,20 +453,65 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
   Resolved r;
   int rc = resolve(o, &r);
   if (rc) return rc;
-  const size_t need = tqr_lstsq_work_size(m, n, nrhs, o);
-  if (work_bytes < need) return TQR_E_WORKSPACE;
+  const LsLayout L = ls_layout(m, n, nrhs, r);
+  if (work_bytes < L.total) return TQR_E_WORKSPACE;
   char *w = static_cast<char *>(work);
-  double *Ac = reinterpret_cast<double *>(w);
-  double *Bc = reinterpret_cast<double *>(w + align_up((size_t)m * n * 8));
-  char *T = w + align_up((size_t)m * n * 8) + align_up((size_t)m * nrhs * 8);
-  const size_t tb = work_bytes - (size_t)(T - w);
+  double *Ac = reinterpret_cast<double *>(w + L.ac);
+  double *Bc = reinterpret_cast<double *>(w + L.bc);
+  char *T = w + L.t;
+  auto *rep = reinterpret_cast<RefineState *>(w + L.report);
   if (hipMemcpy2DAsync(Ac, m * 8, A, lda * 8, m * 8, n, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return TQR_E_HIP;
   if (hipMemcpy2DAsync(Bc, m * 8, B, ldb * 8, m * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return TQR_E_HIP;
-  rc = run_plan(PK_LSTSQ, m, n, Ac, m, Bc, m, nrhs, T, tb, r, info, stream);
+  if (refine_start(rep, stream) != hipSuccess) return TQR_E_HIP;
+  // factorization, Q^T B and R X = (Q^T B)(1:n) in one executor launch
+  rc = run_plan(PK_LSTSQ, m, n, Ac, m, Bc, m, nrhs, T, L.t_bytes, r, info, stream);
   if (rc) return rc;
-  if (hipMemcpy2DAsync(X, ldx * 8, Bc, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+  if (r.update_dtype == TQR_F64) {
+    if (hipMemcpy2DAsync(X, ldx * 8, Bc, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+      return TQR_E_HIP;
+    return TQR_OK;
+  }
+  // Low-precision updates: refine X in FP64 against the caller's A and B.
+  // Square systems use classical refinement, d = R^{-1} (Q^T r)(1:n);
+  // rectangular ones the semi-normal equations with the computed R,
+  // d = R^{-1} R^{-T} A^T r, whose fixed point satisfies A^T r = 0 exactly
+  // (classical refinement would stop at a point with A^T r of the size of
+  // the factorization error times r).  Every iteration is enqueued; the
+  // kernels of the iterations after convergence return at once.
+  const bool square = (m == n);
+  double *xw = reinterpret_cast<double *>(w + L.xw);
+  double *rw = reinterpret_cast<double *>(w + L.rw);
+  double *sw = reinterpret_cast<double *>(w + L.sw);
+  void *part = w + L.part;
+  const double tol = r.refine_tol > 0.0 ? r.refine_tol : 16.0 * 2.220446049250313e-16;
+  const int32_t *skip = &rep->done;
+  if (hipMemcpy2DAsync(xw, n * 8, Bc, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+    return TQR_E_HIP;
+  if (refine_fro(A, lda, m, n, part, stream) != hipSuccess) return TQR_E_HIP;
+  for (int it = 0; it <= r.max_refine; it++) {
+    if (refine_residual(A, lda, m, n, xw, n, B, ldb, nrhs, rw, m, square ? nullptr : sw, n, part, rep,
+                        stream) != hipSuccess)
+      return TQR_E_HIP;
+    if (refine_check(m, n, nrhs, rw, m, square ? nullptr : sw, n, xw, n, B, ldb, part, tol, it, rep, stream) !=
+        hipSuccess)
+      return TQR_E_HIP;
+    if (it == r.max_refine) break;
+    if (square) {
+      rc = run_plan(PK_APPLY, m, n, Ac, m, rw, m, nrhs, T, L.t_bytes, r, info, stream, skip);
+      if (!rc) rc = run_plan(PK_SOLVE, m, n, Ac, m, rw, m, nrhs, T, L.t_bytes, r, info, stream, skip);
+      if (rc) return rc;
+      if (refine_update(n, nrhs, xw, n, rw, m, rep, stream) != hipSuccess) return TQR_E_HIP;
+    } else {
+      rc = run_plan(PK_SOLVET, m, n, Ac, m, sw, n, nrhs, T, L.t_bytes, r, info, stream, skip);
+      if (!rc) rc = run_plan(PK_SOLVE, m, n, Ac, m, sw, n, nrhs, T, L.t_bytes, r, info, stream, skip);
+      if (rc) return rc;
+      if (refine_update(n, nrhs, xw, n, sw, n, rep, stream) != hipSuccess) return TQR_E_HIP;
+    }
+  }
+  if (refine_finish(rep, info, TQR_INFO_NOCONV, stream) != hipSuccess) return TQR_E_HIP;
+  if (hipMemcpy2DAsync(X, ldx * 8, xw, n * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return TQR_E_HIP;
   return TQR_OK;
 }
@@ -503,7 +596,7 @@ void tqr_debug_trace(int64_t *buf, int64_t cap) {
 int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *tasks,
                     int64_t cap) {
   if (m < 1 || n < 1 || n > m) return -1;
-  if (kind < PK_FACTOR || kind > PK_LSTSQ) return -4;
+  if (kind < PK_FACTOR || kind > PK_SOLVET) return -4;
   Resolved r;
   int rc = resolve(o, &r);
   if (rc) return rc;
@@ -525,11 +618,14 @@ int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_
   return (int)nt;
 }
 
-int tqr_debug_succ(int64_t m, int64_t n, const tqr_opts *o, int32_t *off, int32_t *succ, int64_t cap) {
+int tqr_debug_succ(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *off,
+                   int32_t *succ, int64_t cap) {
+  if (m < 1 || n < 1 || n > m) return -1;
+  if (kind < PK_FACTOR || kind > PK_SOLVET) return -4;
   Resolved r;
   int rc = resolve(o, &r);
   if (rc) return rc;
-  auto hp = host_plan(make_key(PK_FACTOR, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), 0, r));
+  auto hp = host_plan(make_key(kind, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), kind == PK_FACTOR ? 0 : nrhs, r));
   if ((int64_t)hp->g.succ.size() > cap) return -1;
   std::copy(hp->g.succ_off.begin(), hp->g.succ_off.end(), off);
   std::copy(hp->g.succ.begin(), hp->g.succ.end(), succ);

@@ -19,6 +19,8 @@ double kind_weight(int kind) {
     case K_TTMQR: return 6.0;
     case K_TRSM: return 1.0;  // nb^3 flops
     case K_GEMM: return 6.0;  // 2 nb^3 flops
+    case K_TRSMT: return 1.0;
+    case K_GEMMT: return 6.0;
     default: return 0.0;
   }
 }
@@ -98,8 +100,23 @@ class Builder {
         }
   }
 
+  // Forward substitution R^T Z = B (R^T lower triangular): for k = 0..q-1,
+  // Z(k) = R(k,k)^{-T} B(k), then B(i) -= R(k,i)^T Z(k) for i > k.
+  void solve_t() {
+    for (int jb = 0; jb < spec_.nbcols; jb++)
+      for (int s = 0; s < spec_.stripes_b; s++)
+        for (int k = 0; k < q_; k++) {
+          emit(K_TRSMT, k, k, k, q_ + jb, s, {&u_[idx(k, k)]}, {xitem(k, q_ + jb, s)});
+          for (int i = k + 1; i < q_; i++) {
+            std::vector<ItemState *> rd = {xitem(k, q_ + jb, s)};
+            for (int sa = 0; sa < spec_.stripes; sa++) rd.push_back(xitem(k, i, sa));
+            emit(K_GEMMT, i, i, k, q_ + jb, s, rd, {xitem(i, q_ + jb, s)});
+          }
+        }
+  }
+
  private:
-  bool solve_only() const { return spec_.solve && !spec_.panels && !spec_.b_updates; }
+  bool solve_only() const { return (spec_.solve || spec_.solve_t) && !spec_.panels && !spec_.b_updates; }
   size_t idx(int i, int k) const { return (size_t)i * q_ + k; }
   ItemState *xitem(int i, int j, int s) { return &x_[((size_t)i * qt_ + j) * smax_ + s]; }
   int stripes_of(int j) const { return j < q_ ? spec_.stripes : spec_.stripes_b; }
@@ -160,7 +177,7 @@ class Builder {
     pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
     double w = kind_weight(kind);
     if (kind >= K_UNMQR && kind <= K_TTMQR) w /= stripes_of(j);
-    if (kind == K_TRSM || kind == K_GEMM) w /= spec_.stripes_b;
+    if (kind == K_TRSM || kind == K_GEMM || kind == K_TRSMT || kind == K_GEMMT) w /= spec_.stripes_b;
     double start = 0.0;
     for (int32_t x : pr) start = std::max(start, g_.finish[x]);
     const double fin = start + w;
@@ -366,6 +383,7 @@ Graph build_graph(const std::vector<Elim> &list, const GraphSpec &spec, std::vec
     for (const Elim &e : list) b.elim(e);
     b.end();
   }
+  if (spec.solve_t) b.solve_t();
   if (spec.solve) b.solve();
   if (zero_t) *zero_t = b.zero_times();
   if (geqrt_t) *geqrt_t = b.geqrt_times();

@@ -47,6 +47,7 @@ struct GraphSpec {
   int stripes_b = 1;     // update tasks per target tile of B
   bool panels = true;    // emit the factor kernels (and A-column updates)
   bool b_updates = false;  // emit updates of the B columns
+  bool solve_t = false;  // emit the forward substitution R^T Z = B (after the above)
   bool solve = false;    // emit the back-substitution R X = B (after the above)
 };
 

@@ -33,6 +33,34 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// FP32-accumulating 16x16 MFMAs (f32 16x16x4 and bf16 16x16x16).  Their
+// lane layout differs from the FP64 one: lane l supplies A[l%16][k] and
+// B[k][l%16] with k = l/16 (f32) or k = 4(l/16) + e for element e of the
+// lane's four bf16 (bf16), and register r of lane l holds
+// D[4(l/16) + r][l%16].
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma_bf16(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+// FP32 -> bfloat16, round to nearest even (finite inputs).
+__device__ __forceinline__ short to_bf16(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ __forceinline__ s4 to_bf16x4(f4 v) {
+  s4 r;
+  r[0] = to_bf16(v[0]);
+  r[1] = to_bf16(v[1]);
+  r[2] = to_bf16(v[2]);
+  r[3] = to_bf16(v[3]);
+  return r;
+}
+
 // Zeroes a loaded value unless `on`, with integer masking.  A select
 // between a load and 0 would be turned by the backend into a branch around
 // the load followed by a full wait, serialising every load of a loop; the
@@ -372,6 +400,215 @@ __device__ __forceinline__ void apply_chunk(const double *__restrict__ V, int64_
   }
 }
 
+// ============================================= low-precision reflector apply
+//
+// apply_chunk's arithmetic with FP32 (P_F32: f32 MFMA) or bfloat16 inputs
+// (P_BF16: bf16 MFMA), both accumulating in FP32.  Storage stays FP64: the
+// target columns are read from FP64, updated in FP32 registers and written
+// back as FP64; V and T are the FP64 values of the panel kernels, rounded
+// when they are fed to the MFMA.  Same structure and staging as apply_chunk,
+// with the FP32 accumulator layout (lane group g holds rows 4g..4g+3 of a
+// 16-row block).
+enum { P_F32 = 1, P_BF16 = 2 };
+
+template <int NB, int IB, int WC, int MODE, int P>
+__device__ __forceinline__ void apply_chunk_lp(const double *__restrict__ V, int64_t ldv, int vrows,
+                                               int vcols, const double *__restrict__ Tf, double *C1,
+                                               int64_t ldc1, double *C2, int64_t ldc2, int c2rows,
+                                               int ncols, bool dma, Smem<NB, IB, WC> &sm) {
+  constexpr int NRB = NB / 16;
+  constexpr int NMB = IB / 16;
+  constexpr int NBLK = NB / IB;
+  constexpr int LDV = Smem<NB, IB, WC>::LDV;
+  constexpr int LDT = Smem<NB, IB, WC>::LDT;
+  const int tid = opaque_tid();
+  const int lane = tid & 63;
+  const int g = lane >> 4;
+  const int c = lane & 15;
+  const int col = (tid >> 6) * 16 + c;
+  const bool ok = col < ncols;
+  const int colc = ok ? col : 0;
+
+  // the whole apply (every block) touches every row of C2
+  f4 c2[NRB];
+#pragma unroll
+  for (int rb = 0; rb < NRB; rb++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int row = rb * 16 + 4 * g + r;
+      c2[rb][r] = (float)zmask(C2[colc * ldc2 + min(row, c2rows - 1)], ok && row < c2rows);
+    }
+
+  constexpr int TPT = (IB * IB + NT - 1) / NT;
+  double tld[TPT];
+  auto load_t = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < TPT; q++) {
+      const int idx = min(tid + NT * q, IB * IB - 1);
+      tld[q] = Tf[(b * IB + idx / IB) * IB + idx % IB];
+    }
+  };
+  auto store_t = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < TPT; q++) {
+      const int idx = tid + NT * q;
+      if (idx < IB * IB) {
+        const int cc = idx / IB, r = idx % IB;
+        sm.TL[buf][cc * LDT + r] = zmask(tld[q], r <= cc);
+      }
+    }
+  };
+  auto v_rows = [&](int b, int &rlo, int &rhi) {
+    rlo = (MODE == M_UNM) ? b * IB : 0;
+    rhi = (MODE == M_TT) ? (b + 1) * IB : NB;
+  };
+  __syncthreads();
+  {
+    int rlo, rhi;
+    v_rows(0, rlo, rhi);
+    if (dma) dma_v<NB, IB, WC>(V, ldv, 0, rlo, rhi, sm.VL[0]);
+    else stage_v<NB, IB, WC, MODE>(V, ldv, vrows, vcols, 0, rlo, rhi, sm.VL[0]);
+    load_t(0);
+  }
+  for (int b = 0; b < NBLK; b++) {
+    const int buf = b & 1;
+    int rlo, rhi;
+    v_rows(b, rlo, rhi);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    store_t(buf);
+    __syncthreads();
+    if (b + 1 < NBLK) {
+      int nlo, nhi;
+      v_rows(b + 1, nlo, nhi);
+      if (dma) dma_v<NB, IB, WC>(V, ldv, b + 1, nlo, nhi, sm.VL[buf ^ 1]);
+      else stage_v<NB, IB, WC, MODE>(V, ldv, vrows, vcols, b + 1, nlo, nhi, sm.VL[buf ^ 1]);
+      load_t(b + 1);
+    }
+    const double *VLb = sm.VL[buf];
+    const double *TLb = sm.TL[buf];
+    const int dlo = b * IB, dhi = (b + 1) * IB;
+    // W = V_b^T C2
+    f4 w[NMB], w2[NMB];
+#pragma unroll
+    for (int mb = 0; mb < NMB; mb++) {
+      w[mb] = f4{0.f, 0.f, 0.f, 0.f};
+      w2[mb] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int rb = 0; rb < NRB; rb++) {
+      if (rb * 16 >= rlo && rb * 16 < rhi) {
+        const bool diag = dma && MODE != M_TS && rb * 16 >= dlo && rb * 16 < dhi;
+#pragma unroll
+        for (int mb = 0; mb < NMB; mb++) {
+          if (P == P_F32) {
+#pragma unroll
+            for (int s = 0; s < 4; s++) {
+              const int row = rb * 16 + 4 * g + s;
+              double a = VLb[(mb * 16 + c) * LDV + row];
+              if (diag) a = vmask<MODE>(a, row, dlo + mb * 16 + c);
+              if (rb & 1) w2[mb] = mfma_f32((float)a, c2[rb][s], w2[mb]);
+              else w[mb] = mfma_f32((float)a, c2[rb][s], w[mb]);
+            }
+          } else {
+            s4 av;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+              const int row = rb * 16 + 4 * g + e;
+              double a = VLb[(mb * 16 + c) * LDV + row];
+              if (diag) a = vmask<MODE>(a, row, dlo + mb * 16 + c);
+              av[e] = to_bf16((float)a);
+            }
+            if (rb & 1) w2[mb] = mfma_bf16(av, to_bf16x4(c2[rb]), w2[mb]);
+            else w[mb] = mfma_bf16(av, to_bf16x4(c2[rb]), w[mb]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int mb = 0; mb < NMB; mb++) w[mb] += w2[mb];
+    f4 c1[NMB];
+    if (MODE != M_UNM) {
+#pragma unroll
+      for (int mb = 0; mb < NMB; mb++) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int row = b * IB + mb * 16 + 4 * g + r;
+          c1[mb][r] = (float)zmask(C1[colc * ldc1 + row], ok);
+        }
+        w[mb] += c1[mb];
+      }
+    }
+    // Y = T_b^T W
+    f4 y[NMB];
+#pragma unroll
+    for (int mb = 0; mb < NMB; mb++) {
+      y[mb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb <= mb; kb++) {
+        if (P == P_F32) {
+#pragma unroll
+          for (int s = 0; s < 4; s++) {
+            const float a = (float)TLb[(mb * 16 + c) * LDT + kb * 16 + 4 * g + s];
+            y[mb] = mfma_f32(a, w[kb][s], y[mb]);
+          }
+        } else {
+          s4 av;
+#pragma unroll
+          for (int e = 0; e < 4; e++) av[e] = to_bf16((float)TLb[(mb * 16 + c) * LDT + kb * 16 + 4 * g + e]);
+          y[mb] = mfma_bf16(av, to_bf16x4(w[kb]), y[mb]);
+        }
+      }
+    }
+    if (MODE != M_UNM) {
+#pragma unroll
+      for (int mb = 0; mb < NMB; mb++) {
+        c1[mb] -= y[mb];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int row = b * IB + mb * 16 + 4 * g + r;
+          if (ok) C1[col * ldc1 + row] = (double)c1[mb][r];
+        }
+      }
+    }
+    // C2 -= V_b Y
+#pragma unroll
+    for (int rb = 0; rb < NRB; rb++) {
+      if (rb * 16 >= rlo && rb * 16 < rhi) {
+        const bool diag = dma && MODE != M_TS && rb * 16 >= dlo && rb * 16 < dhi;
+#pragma unroll
+        for (int kb = 0; kb < NMB; kb++) {
+          if (P == P_F32) {
+#pragma unroll
+            for (int s = 0; s < 4; s++) {
+              const int kk = kb * 16 + 4 * g + s;
+              double a = VLb[kk * LDV + rb * 16 + c];
+              if (diag) a = vmask<MODE>(a, rb * 16 + c, dlo + kk);
+              c2[rb] = mfma_f32(-(float)a, y[kb][s], c2[rb]);
+            }
+          } else {
+            s4 av;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+              const int kk = kb * 16 + 4 * g + e;
+              double a = VLb[kk * LDV + rb * 16 + c];
+              if (diag) a = vmask<MODE>(a, rb * 16 + c, dlo + kk);
+              av[e] = to_bf16(-(float)a);
+            }
+            c2[rb] = mfma_bf16(av, to_bf16x4(y[kb]), c2[rb]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int rb = 0; rb < NRB; rb++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int row = rb * 16 + 4 * g + r;
+      if (ok && row < c2rows) C2[col * ldc2 + row] = (double)c2[rb][r];
+    }
+}
+
 // ============================================================ panel kernels
 //
 // GEQRT (M_UNM), TTQRT (M_TT), TSQRT (M_TS) on one tile, blocked by IB:
@@ -593,7 +830,7 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
 // Both keep the chunk in registers in the MFMA accumulator layout.
 template <int NB, int IB, int WC>
 __device__ __forceinline__ void gemm_tile(const double *R, int64_t ldr, int nk, const double *X, int64_t ldx,
-                          double *C, int64_t ldc, int crows, int ncols, Smem<NB, IB, WC> &sm) {
+                          double *C, int64_t ldc, int crows, int ncols, bool trans, Smem<NB, IB, WC> &sm) {
   constexpr int NRB = NB / 16, RBW = (NRB + 3) / 4, NCB = WC / 16;
   constexpr int LDV = Smem<NB, IB, WC>::LDV, LDW = Smem<NB, IB, WC>::LDW;
   const int tid = opaque_tid(), w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
@@ -608,9 +845,16 @@ __device__ __forceinline__ void gemm_tile(const double *R, int64_t ldr, int nk, 
         acc[t][cb][r] = (w + 4 * t < NRB && row < crows && col < ncols) ? C[col * ldc + row] : 0.0;
       }
   for (int b = 0; b * IB < nk; b++) {
-    for (int idx = tid; idx < IB * NB; idx += NT) {
-      const int cc = idx / NB, r = idx % NB, kc = b * IB + cc;
-      sm.VL[0][cc * LDV + r] = (kc < nk) ? R[kc * ldr + r] : 0.0;
+    if (!trans) {
+      for (int idx = tid; idx < IB * NB; idx += NT) {
+        const int cc = idx / NB, r = idx % NB, kc = b * IB + cc;
+        sm.VL[0][cc * LDV + r] = (kc < nk) ? R[kc * ldr + r] : 0.0;
+      }
+    } else {  // R^T: element (r, kc) is R(kc, r); columns r >= crows lie outside the matrix
+      for (int idx = tid; idx < IB * NB; idx += NT) {
+        const int r = idx / IB, cc = idx % IB, kc = b * IB + cc;
+        sm.VL[0][cc * LDV + r] = (kc < nk && r < crows) ? R[r * ldr + kc] : 0.0;
+      }
     }
     for (int idx = tid; idx < IB * WC; idx += NT) {
       const int kk = idx / WC, n = idx % WC, kr = b * IB + kk;
@@ -824,6 +1068,81 @@ __device__ __forceinline__ void trsm_waves(const double *R, int64_t ldr, int nk,
   }
 }
 
+// Sum over the 64 lanes of a wave, returned (wave-uniform) to every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = group_sum<16>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Forward substitution R^T z = y (R upper triangular, so R^T is lower) for
+// right-hand sides in groups of two columns per wave, lanes holding rows as
+// in trsm_waves.  Left-looking: row r needs column r of R above the
+// diagonal, dotted with the solved part of z (a wave reduction), which keeps
+// R's columns contiguous in LDS exactly as the backward solve stages them.
+template <int NB, int IB, int WC>
+__device__ __forceinline__ void trsmt_waves(const double *R, int64_t ldr, int nk, double *X, int64_t ldx,
+                                            int ncols, int row0, int32_t *singular, Smem<NB, IB, WC> &sm) {
+  constexpr int U = (NB + 63) / 64;
+  constexpr int CB = NB < 64 ? NB : 64;
+  constexpr int CPW = 2;
+  double *Ls = &sm.VL[0][0];
+  const int tid = opaque_tid();
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  for (int cg = 0; cg < ncols; cg += CPW * (NT / 64)) {
+    double y[CPW][U], z[CPW][U];
+#pragma unroll
+    for (int c = 0; c < CPW; c++) {
+      const int n = min(cg + w + (NT / 64) * c, ncols - 1);
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int row = u * 64 + lane;
+        y[c][u] = zmask(X[n * ldx + min(row, nk - 1)], row < nk);
+        z[c][u] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int ub = 0; ub < U; ub++) {
+      const int c0 = ub * CB;
+      if (c0 < nk) {
+        const int c1 = min(nk, c0 + CB);
+        __syncthreads();
+        for (int idx = tid; idx < (c1 - c0) * c1; idx += NT) {
+          const int cc = idx / c1, row = idx % c1;
+          Ls[cc * NB + row] = R[(c0 + cc) * ldr + row];
+        }
+        __syncthreads();
+        for (int l = 0; l < c1 - c0; l++) {
+          const int r = c0 + l;
+          const double *colr = Ls + l * NB;
+          const double d = colr[r];
+          if (d == 0.0 && w == 0 && lane == 0) atomicMin(singular, row0 + r + 1);
+          double rv[U];
+#pragma unroll
+          for (int u = 0; u <= ub; u++) rv[u] = colr[min(u * 64 + lane, c1 - 1)];
+#pragma unroll
+          for (int c = 0; c < CPW; c++) {
+            double p = 0.0;
+#pragma unroll
+            for (int u = 0; u <= ub; u++) p = fma(rv[u], z[c][u], p);  // z is zero from row r on
+            const double zr = (readlane_d(y[c][ub], l) - wave_sum(p)) / d;
+            z[c][ub] = (lane == l) ? zr : z[c][ub];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; c++) {
+      const int n = cg + w + (NT / 64) * c;
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int row = u * 64 + lane;
+        if (n < ncols && row < nk) X[n * ldx + row] = z[c][u];
+      }
+    }
+  }
+}
+
 // ================================================================== tasks
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
@@ -849,7 +1168,7 @@ __device__ __forceinline__ void run_task(const ExecArgs &a, const Task &t, Smem<
                                    Tof(t.i, t.k, 1), sm);
     return;
   }
-  if (kind == K_TRSM || kind == K_GEMM) {
+  if (kind == K_TRSM || kind == K_GEMM || kind == K_TRSMT || kind == K_GEMMT) {
     // right-hand-side tile column j - q; stripe of it
     const int jb = t.j - a.q;
     const int nkk = (int)min((int64_t)NB, a.n - (int64_t)t.k * NB);
@@ -865,9 +1184,16 @@ __device__ __forceinline__ void run_task(const ExecArgs &a, const Task &t, Smem<
       else if (kind == K_TRSM)
         trsm_tile<NB, IB, WC>(tileA(t.k, t.k), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
                               a.ldb, nc, t.k * NB, &a.ctl->pad[0], sm);
-      else
+      else if (kind == K_TRSMT)
+        trsmt_waves<NB, IB, WC>(tileA(t.k, t.k), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
+                                a.ldb, nc, t.k * NB, &a.ctl->pad[0], sm);
+      else if (kind == K_GEMM)
         gemm_tile<NB, IB, WC>(tileA(t.i, t.k), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
-                              a.ldb, Bc + (int64_t)cs * a.ldb + (int64_t)t.i * NB, a.ldb, NB, nc, sm);
+                              a.ldb, Bc + (int64_t)cs * a.ldb + (int64_t)t.i * NB, a.ldb, NB, nc, false, sm);
+      else  // K_GEMMT: rows of block i (the last one may be ragged) from R(k, i)^T
+        gemm_tile<NB, IB, WC>(tileA(t.k, t.i), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
+                              a.ldb, Bc + (int64_t)cs * a.ldb + (int64_t)t.i * NB, a.ldb,
+                              (int)min((int64_t)NB, a.n - (int64_t)t.i * NB), nc, true, sm);
     }
     return;
   }
@@ -891,9 +1217,35 @@ __device__ __forceinline__ void run_task(const ExecArgs &a, const Task &t, Smem<
   const int cbeg = t.stripe * sw;
   const int cend = imin(ncols, cbeg + sw);
   const bool dma = a.dma_ok && NB >= 128 && vrows == NB && vcols == NB;
+  const int lp = (t.j < a.q) ? a.update_dtype : 0;  // B's columns always in FP64
   for (int cs = cbeg; cs < cend; cs += CHUNK) {
     const int nc = imin(CHUNK, cend - cs);
     double *C2 = base + (int64_t)cs * ld + (int64_t)t.i * NB;
+    if (lp != 0) {
+      double *C1 = base + (int64_t)cs * ld + (int64_t)t.piv * NB;
+      if (lp == P_F32) {
+        if (kind == K_UNMQR)
+          apply_chunk_lp<NB, IB, WC, M_UNM, P_F32>(V, lda, vrows, vcols, Tof(t.i, t.k, 0), nullptr, 0, C2, ld,
+                                                   vrows, nc, dma, sm);
+        else if (kind == K_TTMQR)
+          apply_chunk_lp<NB, IB, WC, M_TT, P_F32>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld,
+                                                  vrows, nc, dma, sm);
+        else
+          apply_chunk_lp<NB, IB, WC, M_TS, P_F32>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld,
+                                                  vrows, nc, dma, sm);
+      } else {
+        if (kind == K_UNMQR)
+          apply_chunk_lp<NB, IB, WC, M_UNM, P_BF16>(V, lda, vrows, vcols, Tof(t.i, t.k, 0), nullptr, 0, C2,
+                                                    ld, vrows, nc, dma, sm);
+        else if (kind == K_TTMQR)
+          apply_chunk_lp<NB, IB, WC, M_TT, P_BF16>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld,
+                                                   vrows, nc, dma, sm);
+        else
+          apply_chunk_lp<NB, IB, WC, M_TS, P_BF16>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld,
+                                                   vrows, nc, dma, sm);
+      }
+      continue;
+    }
     if (kind == K_UNMQR) {
       apply_chunk<NB, IB, WC, M_UNM>(V, lda, vrows, vcols, Tof(t.i, t.k, 0), nullptr, 0, C2, ld,
                                      vrows, nc, 0, NB / IB, false, dma, sm);
@@ -935,7 +1287,11 @@ __device__ __forceinline__ void st_release(int32_t *p, int v) {
 
 // Resets the executor state: dependency counts, queue (initially ready
 // tasks first, the rest empty = -1) and control block.
+// (templated on the tile size only so that each per-configuration object
+// defines its own instance)
+template <int NB>
 __global__ void exec_reset(ExecArgs a) {
+  if (a.skip && *a.skip) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < a.ntasks; x += stride) {
     a.indeg[x] = a.indeg0[x];
@@ -957,6 +1313,7 @@ __global__ void exec_reset(ExecArgs a) {
 template <int NB, int IB, int WC>
 __global__ __launch_bounds__(NT, 1) void exec_persistent(ExecArgs a) {
   __shared__ Smem<NB, IB, WC> sm;
+  if (a.skip && *a.skip) return;
   ExecCtl *ctl = a.ctl;
   for (;;) {
     // Every iteration starts with all threads past their last use of LDS.
@@ -1015,6 +1372,7 @@ __global__ __launch_bounds__(NT, 1) void exec_persistent(ExecArgs a) {
 template <int NB, int IB, int WC>
 __global__ __launch_bounds__(NT, 1) void exec_one(ExecArgs a, int tid) {
   __shared__ Smem<NB, IB, WC> sm;
+  if (a.skip && *a.skip) return;
   const int64_t tstart = a.trace ? (int64_t)wall_clock64() : 0;
   run_task<NB, IB, WC>(a, load_task(a.tasks + tid), sm);
   __syncthreads();
@@ -1027,7 +1385,9 @@ __global__ __launch_bounds__(NT, 1) void exec_one(ExecArgs a, int tid) {
   }
 }
 
+template <int NB>
 __global__ void exec_finish(ExecArgs a, int32_t *info) {
+  if (a.skip && *a.skip) return;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const int e = a.ctl->error;
     const int z = a.ctl->pad[0];
@@ -1040,15 +1400,15 @@ template <int NB, int IB, int WC>
 static hipError_t launch_cfg(const ExecArgs &a, int mode, int grid, const int32_t *order,
                              int32_t *info, hipStream_t s) {
   const int rgrid = (int)((a.ntasks + 255) / 256);
-  hipLaunchKernelGGL(exec_reset, dim3(rgrid < 1 ? 1 : (rgrid > 1024 ? 1024 : rgrid)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(exec_reset<NB>, dim3(rgrid < 1 ? 1 : (rgrid > 1024 ? 1024 : rgrid)), dim3(256), 0, s, a);
   if (mode == 1) {
     for (int t = 0; t < a.ntasks; t++)
       hipLaunchKernelGGL((exec_one<NB, IB, WC>), dim3(1), dim3(NT), 0, s, a, order[t]);
-    hipLaunchKernelGGL(exec_finish, dim3(1), dim3(64), 0, s, a, info);
+    hipLaunchKernelGGL(exec_finish<NB>, dim3(1), dim3(64), 0, s, a, info);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((exec_persistent<NB, IB, WC>), dim3(grid), dim3(NT), 0, s, a);
-  hipLaunchKernelGGL(exec_finish, dim3(1), dim3(64), 0, s, a, info);
+  hipLaunchKernelGGL(exec_finish<NB>, dim3(1), dim3(64), 0, s, a, info);
   return hipGetLastError();
 }
 
@@ -1060,48 +1420,21 @@ static int occupancy_cfg() {
   return nb < 1 ? 1 : nb;
 }
 
-// Stripe width granule (columns per register-resident chunk) of a config.
-int chunk_width(int nb, int ib) {
-  (void)ib;
-  return nb < CHUNK ? nb : CHUNK;
-}
-
-#ifdef TQR_ONE_CONFIG
-#define TQR_CONFIGS(X) X(256, 32, 64)
-#else
-#define TQR_CONFIGS(X) \
-  X(32, 16, 64)        \
-  X(64, 16, 64)        \
-  X(64, 32, 64)        \
-  X(128, 32, 64)       \
-  X(256, 32, 64)
+// This file is compiled once per tile configuration (TQR_CFG_NB,
+// TQR_CFG_IB); each object exports that configuration's launch and
+// occupancy functions, and configs.cpp dispatches on (nb, ib).
+#ifndef TQR_CFG_NB
+#error "compile with -DTQR_CFG_NB=<nb> -DTQR_CFG_IB=<ib>"
 #endif
+#define TQR_FN3(name, a, b) name##_##a##_##b
+#define TQR_FN2(name, a, b) TQR_FN3(name, a, b)
+#define TQR_FN(name) TQR_FN2(name, TQR_CFG_NB, TQR_CFG_IB)
 
-// mode: 0 persistent, 1 sequential (one launch per task in the host-side
-// topological order `order`).
-hipError_t launch_exec(const ExecArgs &a, int mode, int grid, const int32_t *order, int32_t *info,
-                       hipStream_t s) {
-#define X(NB, IB, WC) \
-  if (a.nb == NB && a.ib == IB) return launch_cfg<NB, IB, WC>(a, mode, grid, order, info, s);
-  TQR_CONFIGS(X)
-#undef X
-  return hipErrorInvalidValue;
+hipError_t TQR_FN(launch_exec)(const ExecArgs &a, int mode, int grid, const int32_t *order, int32_t *info,
+                               hipStream_t s) {
+  return launch_cfg<TQR_CFG_NB, TQR_CFG_IB, CHUNK>(a, mode, grid, order, info, s);
 }
 
-int exec_occupancy(int nb, int ib) {
-#define X(NB, IB, WC) \
-  if (nb == NB && ib == IB) return occupancy_cfg<NB, IB, WC>();
-  TQR_CONFIGS(X)
-#undef X
-  return 0;
-}
-
-bool config_supported(int nb, int ib) {
-#define X(NB, IB, WC) \
-  if (nb == NB && ib == IB) return true;
-  TQR_CONFIGS(X)
-#undef X
-  return false;
-}
+int TQR_FN(exec_occupancy)() { return occupancy_cfg<TQR_CFG_NB, TQR_CFG_IB, CHUNK>(); }
 
 }  // namespace tqr

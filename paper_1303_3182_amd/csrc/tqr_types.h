@@ -15,7 +15,9 @@ enum Kind : int32_t {
   K_TTMQR = 5,  // apply TTQRT(i,piv,k)'s Q^T to tiles (piv,j), (i,j)
   K_TRSM = 6,   // X(k,j) <- R(k,k)^{-1} X(k,j)
   K_GEMM = 7,   // X(i,j) <- X(i,j) - R(i,k) X(k,j)
-  K_COUNT = 8
+  K_TRSMT = 8,  // X(k,j) <- R(k,k)^{-T} X(k,j)
+  K_GEMMT = 9,  // X(i,j) <- X(i,j) - R(k,i)^T X(k,j), i > k
+  K_COUNT = 10
 };
 
 // One task of the executor's graph.  Tile coordinates are 0-based; column
@@ -62,10 +64,11 @@ struct ExecArgs {
   int32_t sw;       // stripe width of updates of A's columns (columns per task)
   int32_t sw_b;     // stripe width of tasks on B's columns
   int32_t dma_ok;   // A is 16-byte aligned with even lda: tiles may be DMA'd to LDS
-  int32_t pad_;
+  int32_t update_dtype;  // arithmetic of the updates of A's columns: 0 FP64, 1 FP32, 2 BF16
   int64_t spin_limit;  // watchdog, in wall-clock ticks
   int64_t *trace;      // optional: per task {start, end, workgroup, xcc}
   int64_t trace_cap;   // tasks that fit in `trace`
+  const int32_t *skip; // optional: the launch does nothing if *skip != 0
 };
 
 }  // namespace tqr

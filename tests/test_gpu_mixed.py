@@ -1,0 +1,99 @@
+"""Mixed precision: FP32 / BF16 MFMA trailing updates with FP64 panels, then
+FP64 refinement, through the C ABI, against the FP64 oracle.
+
+Bars:
+- the low-precision factorization itself is backward stable to the update
+  precision: ||Q^T A - [R; 0]||_F / ||A||_F <= c u_low (u = 2^-24 for FP32,
+  2^-8 for BF16 with its 8-bit significand and FP32 accumulation), with
+  c = 8 sqrt(n) (rounding of each of the O(q) block updates of every entry);
+- after refinement the solution meets the FP64 bar: its normwise backward
+  error, measured by the oracle in extended precision, is <= 50 eps
+  (Stewart's bound for rectangular problems, Rigal-Gaches for square ones),
+  and it agrees with the oracle's FP64 solution to the conditioning bound."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1303_3182_amd as T
+import synth
+from oracle import householder as H
+from tests.gpu_util import EPS, case
+
+pytestmark = pytest.mark.gpu
+
+U_LOW = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8}
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("kernels", ["tt", "hybrid"])
+def test_low_precision_factor_backward_error(dtype, kernels):
+    for (m, n, nb) in [(1024, 512, 128), (700, 300, 64), (512, 512, 256)]:
+        case("mixed factor %s %s m=%d n=%d nb=%d" % (dtype, kernels, m, n, nb))
+        A0 = synth.gaussian(m, n, 5 + m)
+        o = T.default_opts(nb=nb, tree="greedy", kernels=kernels, update_dtype=dtype)
+        A = T.colmajor(A0)
+        A, W = T.factor(A, o, nrhs=n)
+        Bm = T.colmajor(A0)
+        T.apply_qt(A, W, Bm, o)   # FP64 replay of the stored reflectors
+        torch.cuda.synchronize()
+        R = np.triu(A.cpu().numpy()[:n])
+        QtA = Bm.cpu().numpy()
+        QtA[:n] -= R
+        be = np.linalg.norm(QtA) / np.linalg.norm(A0)
+        assert be <= 8 * np.sqrt(n) * U_LOW[dtype], (dtype, be)
+        # and it is not the FP64 path in disguise: the error is well above FP64's
+        assert be > 100 * EPS, (dtype, be)
+
+
+def _lstsq(A0, B0, o):
+    m, n = A0.shape
+    nrhs = B0.shape[1]
+    work = T.lstsq_workspace(m, n, nrhs, o)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    X = T.lstsq(T.colmajor(A0), T.colmajor(B0), o, work=work, info=info)
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), int(info.item()), T.refine_report(work)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_refined_rectangular_least_squares(dtype):
+    for (m, n, nb, nrhs) in [(1000, 300, 64, 1), (2048, 512, 128, 2), (3000, 257, 256, 1)]:
+        case("mixed lstsq %s m=%d n=%d nb=%d nrhs=%d" % (dtype, m, n, nb, nrhs))
+        A0 = synth.gaussian(m, n, 17 + m)
+        B0 = synth.gaussian_rhs(m, nrhs, 17 + m)
+        o = T.default_opts(nb=nb, tree="grasap", update_dtype=dtype, max_refine=20)
+        X, info, rep = _lstsq(A0, B0, o)
+        assert info == 0 and rep["done"] == 1, (info, rep)
+        Ro, Vo, tau = H.qr(A0)
+        QtB = H.apply_qt(Vo, tau, B0)
+        kap = np.linalg.cond(A0)
+        for c in range(nrhs):
+            assert H.ls_backward_error(A0, B0[:, c], X[:, c]) <= 50 * EPS, rep
+            xo = H.back_substitute(Ro, QtB[:n, c])
+            assert np.linalg.norm(X[:, c] - xo) <= 100 * kap ** 2 * EPS * np.linalg.norm(xo)
+        # refinement had work to do, and each step helped
+        assert rep["iterations"] >= 1
+        hist = rep["history"]
+        assert hist[0] > 50 * EPS
+
+
+@pytest.mark.parametrize("dtype,kappa", [("f32", 1e2), ("f32", 1e5), ("bf16", 1e2)])
+def test_refined_square_conditioned(dtype, kappa):
+    n, nb = 512, 128
+    case("mixed square %s kappa=%g n=%d" % (dtype, kappa, n))
+    A0, x0, b0 = synth.conditioned(n, kappa, 3)
+    o = T.default_opts(nb=nb, tree="greedy", update_dtype=dtype, max_refine=20)
+    X, info, rep = _lstsq(A0, b0[:, None], o)
+    assert info == 0 and rep["done"] == 1, (info, rep)
+    x = X[:, 0]
+    assert H.ls_backward_error(A0, b0, x) <= 50 * EPS
+    Ro, Vo, tau = H.qr(A0)
+    xo = H.back_substitute(Ro, H.apply_qt(Vo, tau, b0)[:n])
+    assert np.linalg.norm(x - xo) <= 100 * kappa * EPS * np.linalg.norm(xo)
+
+
+def test_fp64_lstsq_report_untouched_by_refinement():
+    A0 = synth.gaussian(300, 100, 1)
+    B0 = synth.gaussian_rhs(300, 1, 1)
+    X, info, rep = _lstsq(A0, B0, T.default_opts(nb=64))
+    assert info == 0 and rep["done"] == 0 and rep["iterations"] == 0 and rep["history"] == []
