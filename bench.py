@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--stripes", type=int, default=0)
     ap.add_argument("--cpu-sample-cols", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed", nargs="*", default=["f32", "bf16"],
+                    help="also time the solve with these update dtypes + FP64 refinement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the factorization runs on a single device "
@@ -123,11 +125,38 @@ def main():
 
     # accuracy of the last step's solution: Stewart's one-sided backward
     # error bound ||A^T r|| / (||A||_F ||r||) in extended precision
-    x = X[:, 0].cpu().numpy()
     Al = A0.astype(np.longdouble)
-    r = b0[:, 0].astype(np.longdouble) - Al @ x.astype(np.longdouble)
-    be = float(np.linalg.norm((Al.T @ r).astype(np.float64)) /
-               (np.linalg.norm(A0) * np.linalg.norm(r.astype(np.float64))))
+
+    def backward_error(x):
+        r = b0[:, 0].astype(np.longdouble) - Al @ x.astype(np.longdouble)
+        return float(np.linalg.norm((Al.T @ r).astype(np.float64)) /
+                     (np.linalg.norm(A0) * np.linalg.norm(r.astype(np.float64))))
+
+    be = backward_error(X[:, 0].cpu().numpy())
+
+    # the same least-squares solve with low-precision trailing updates and
+    # FP64 refinement to the FP64 backward error
+    mixed = {}
+    for dt in args.mixed:
+        om = T.default_opts(nb=nb, ib=args.ib, tree=args.tree, kernels=args.kernels, stripes=args.stripes,
+                            update_dtype=dt, max_refine=20)
+        wm = T.lstsq_workspace(m, n, 1, om, dev)
+        for w in range(args.warmup):
+            T.lstsq(A, b, om, X=X, work=wm, info=info)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            T.lstsq(A, b, om, X=X, work=wm, info=info)
+        torch.cuda.synchronize()
+        mms = (time.perf_counter() - t0) / args.steps * 1e3
+        rep = T.refine_report(wm)
+        inf = int(info.item())
+        mbe = backward_error(X[:, 0].cpu().numpy())
+        log("mixed %s: %.3f ms/step, %d refinement steps, backward error %.2e (info %d)" %
+            (dt, mms, rep["iterations"], mbe, inf))
+        mixed[dt] = {"ms_per_step": mms, "value": qr_flops(m, n) / (mms / 1e3) / 1e12, "unit": "TFLOP/s",
+                     "speedup_vs_fp64": ms / mms, "refine_steps": rep["iterations"], "converged": rep["done"],
+                     "info": inf, "ls_backward_error": mbe, "equal_fp64_error": bool(mbe <= 50 * 2.0 ** -52)}
 
     flops = qr_flops(m, n)
     achieved = flops / (factor_ms / 1e3) / 1e12
@@ -150,6 +179,7 @@ def main():
                    "kernels": args.kernels, "precision": "plain FP64"},
         "executor_ms": factor_ms,
         "ls_backward_error": be,
+        "mixed_precision": mixed,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
                      "kernel": "exec_persistent (least-squares task graph: factor, Q^T b, R x = c)"},

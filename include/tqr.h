@@ -176,6 +176,43 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
               int64_t ldb, double *X, int64_t ldx, void *work, size_t work_bytes,
               const tqr_opts *o, int32_t *info, hipStream_t stream);
 
+/* ---------------------------------------------------- batched least squares
+ *
+ * Many independent least-squares problems min ||A_x X_x - B_x||, each with
+ * its own m_x >= n_x (ragged), nrhs right-hand sides each, in ONE executor
+ * launch: the task graphs of all problems form one graph with one ready
+ * queue ordered by critical-path length (bottom level) across problems.
+ * Host arrays of sizes and of device pointers; the matrices are device
+ * memory, column-major, and are not modified.  Tile size nb/ib come from
+ * opts and are shared by the batch; opts.tree = TQR_AUTO picks per problem
+ * the tree with the shortest tiled critical path (section "Critical paths")
+ * among FlatTree, BinaryTree, Fibonacci, Greedy and GrASAP, else every
+ * problem uses opts.tree.  With opts.update_dtype != TQR_F64 each problem
+ * is refined in FP64 by the semi-normal equations (see tqr_refine_report);
+ * the reports of all problems are at the start of `work`, one
+ * tqr_refine_report per problem, contiguous.  info: NULL or a device array
+ * of count int32 (meaning as for tqr_lstsq).  Arguments: -1 count < 1,
+ * -2 bad m / n, -4 nrhs < 1, -5 bad A / lda, -7 bad B / ldb, -9 bad X / ldx,
+ * -11 work NULL. */
+size_t tqr_lstsq_batched_work_size(int32_t count, const int64_t *m, const int64_t *n, int64_t nrhs,
+                                   const tqr_opts *o); /* o->nb == 0: largest over the built configs */
+int tqr_lstsq_batched(int32_t count, const int64_t *m, const int64_t *n, int64_t nrhs,
+                      const double *const *A, const int64_t *lda, const double *const *B,
+                      const int64_t *ldb, double *const *X, const int64_t *ldx, void *work,
+                      size_t work_bytes, const tqr_opts *o, int32_t *info, hipStream_t stream);
+
+/* Autotuner for a batch: runs tqr_lstsq_batched with every built (nb, ib)
+ * configuration (tree and the other options from *o), times each on
+ * `stream` with HIP events, and writes the fastest nb, ib into *o
+ * (best_ms: NULL or its time).  Synchronous.  The choice is cached per
+ * (shapes, nrhs, options); a cached call returns at once with *best_ms =
+ * -1.  work must hold tqr_lstsq_batched_work_size with o->nb = 0.  X
+ * receives the solutions of the last run. */
+int tqr_autotune_batched(int32_t count, const int64_t *m, const int64_t *n, int64_t nrhs,
+                         const double *const *A, const int64_t *lda, const double *const *B,
+                         const int64_t *ldb, double *const *X, const int64_t *ldx, void *work,
+                         size_t work_bytes, tqr_opts *o, float *best_ms, hipStream_t stream);
+
 /* ----------------------------------------------- host-only list services */
 
 /* Elimination list of `tree` (param: PlasmaTree BS / GrASAP i) for p x q

@@ -13,4 +13,5 @@ from ._binding import (  # noqa: F401
     library_path, tqr_apply_qt, tqr_factor, tqr_factor_ex, tqr_graph_stats, tqr_lstsq,
     tqr_lstsq_work_size, tqr_solve_r, tqr_tree_cp, tqr_tree_list, tqr_workspace_size,
 )
-from .api import apply_qt, colmajor, factor, lstsq, lstsq_workspace, refine_report, solve_r, workspace  # noqa: F401
+from .api import (apply_qt, autotune_batched, colmajor, factor, lstsq, lstsq_batched,  # noqa: F401
+                  lstsq_batched_workspace, lstsq_workspace, refine_report, refine_reports, solve_r, workspace)  # noqa: F401

@@ -44,6 +44,7 @@ def lib():
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         op = ctypes.POINTER(Opts)
         i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+        vpp = ctypes.POINTER(ctypes.c_void_p)
         sig = {
             "tqr_default_opts": (None, [op]),
             "tqr_workspace_size": (sz, [i64, i64, i64, op]),
@@ -57,6 +58,11 @@ def lib():
             "tqr_tree_cp": (i64, [i32, i32, i32, i32, i32, i64p, i64p]),
             "tqr_graph_stats": (ctypes.c_int, [i64, i64, op, i64p, i64p]),
             "tqr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+            "tqr_lstsq_batched_work_size": (sz, [i32, i64p, i64p, i64, op]),
+            "tqr_lstsq_batched": (ctypes.c_int, [i32, i64p, i64p, i64, vpp, i64p, vpp, i64p, vpp, i64p, vp, sz, op,
+                                                 vp, vp]),
+            "tqr_autotune_batched": (ctypes.c_int, [i32, i64p, i64p, i64, vpp, i64p, vpp, i64p, vpp, i64p, vp, sz,
+                                                    op, ctypes.POINTER(ctypes.c_float), vp]),
             "tqr_debug_trace": (None, [vp, i64]),
             "tqr_debug_timing": (None, [i32]),
             "tqr_debug_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), i64p]),

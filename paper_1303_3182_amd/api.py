@@ -98,3 +98,86 @@ def refine_report(work):
     vals = np.frombuffer(raw[8:], dtype=np.float64)
     hist = [float(v) for v in vals[1:] if v >= 0.0]
     return {"done": int(done), "iterations": int(iters), "backward_error": float(vals[0]), "history": hist}
+
+
+def _i64arr(v):
+    import ctypes
+    return (ctypes.c_int64 * len(v))(*[int(x) for x in v])
+
+
+def _ptrarr(ts):
+    import ctypes
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+def lstsq_batched_workspace(shapes, nrhs=1, opts=None, device="cuda"):
+    """Workspace for lstsq_batched over `shapes` [(m, n), ...]; opts.nb = 0
+    sizes it for every built configuration (as the autotuner needs)."""
+    ms = _i64arr([m for m, _ in shapes])
+    ns = _i64arr([n for _, n in shapes])
+    nbytes = B.lib().tqr_lstsq_batched_work_size(len(shapes), ms, ns, nrhs, B._opts_ptr(opts))
+    if nbytes == 0:
+        raise B.TqrError("invalid shapes/options for lstsq_batched")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _batch_args(As, Bs, Xs):
+    ms = _i64arr([a.shape[0] for a in As])
+    ns = _i64arr([a.shape[1] for a in As])
+    return (ms, ns, _ptrarr(As), _i64arr([_ld(a) for a in As]), _ptrarr(Bs), _i64arr([_ld(b) for b in Bs]),
+            _ptrarr(Xs), _i64arr([_ld(x) for x in Xs]))
+
+
+def lstsq_batched(As, Bs, opts=None, Xs=None, work=None, info=None):
+    """Least-squares solutions of a ragged batch in one executor launch.
+    As[x]: m_x x n_x, Bs[x]: m_x x nrhs (column-major float64 CUDA tensors);
+    returns the list of X[x] (n_x x nrhs)."""
+    count = len(As)
+    nrhs = Bs[0].shape[1]
+    dev = As[0].device
+    if Xs is None:
+        Xs = [torch.empty((nrhs, a.shape[1]), dtype=torch.float64, device=dev).t() for a in As]
+    if work is None:
+        work = lstsq_batched_workspace([tuple(a.shape) for a in As], nrhs, opts, dev)
+    ms, ns, pa, la, pb, lb, px, lx = _batch_args(As, Bs, Xs)
+    rc = B.lib().tqr_lstsq_batched(count, ms, ns, nrhs, pa, la, pb, lb, px, lx, work.data_ptr(), work.numel(),
+                                   B._opts_ptr(opts), None if info is None else info.data_ptr(), _stream())
+    B._check(rc, "tqr_lstsq_batched")
+    return Xs
+
+
+def autotune_batched(As, Bs, opts, Xs=None, work=None):
+    """Times every built (nb, ib) on this batch and sets opts.nb, opts.ib to
+    the fastest; returns its time in ms (-1 if the choice was cached)."""
+    import ctypes
+    count = len(As)
+    nrhs = Bs[0].shape[1]
+    dev = As[0].device
+    if Xs is None:
+        Xs = [torch.empty((nrhs, a.shape[1]), dtype=torch.float64, device=dev).t() for a in As]
+    if work is None:
+        o0 = B.Opts()
+        ctypes.memmove(ctypes.byref(o0), ctypes.byref(opts), ctypes.sizeof(B.Opts))
+        o0.nb = 0
+        work = lstsq_batched_workspace([tuple(a.shape) for a in As], nrhs, o0, dev)
+    ms, ns, pa, la, pb, lb, px, lx = _batch_args(As, Bs, Xs)
+    best = ctypes.c_float(0.0)
+    rc = B.lib().tqr_autotune_batched(count, ms, ns, nrhs, pa, la, pb, lb, px, lx, work.data_ptr(), work.numel(),
+                                      ctypes.byref(opts), ctypes.byref(best), _stream())
+    B._check(rc, "tqr_autotune_batched")
+    return best.value
+
+
+def refine_reports(work, count):
+    """The per-problem refinement reports at the start of a batched workspace."""
+    import numpy as np
+    rec = 8 + 8 + 8 * B.REFINE_HISTORY
+    raw = work[:rec * count].cpu().numpy().tobytes()
+    out = []
+    for x in range(count):
+        r = raw[rec * x:rec * (x + 1)]
+        done, iters = np.frombuffer(r[:8], dtype=np.int32)
+        vals = np.frombuffer(r[8:], dtype=np.float64)
+        out.append({"done": int(done), "iterations": int(iters), "backward_error": float(vals[0]),
+                    "history": [float(v) for v in vals[1:] if v >= 0.0]})
+    return out

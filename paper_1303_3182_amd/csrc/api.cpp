@@ -22,6 +22,7 @@ hipError_t launch_exec(const ExecArgs &a, int mode, int grid, const int32_t *ord
 int exec_occupancy(int nb, int ib);
 bool config_supported(int nb, int ib);
 int chunk_width(int nb, int ib);
+int config_list(int *nb, int *ib, int cap);
 }  // namespace tqr
 
 using namespace tqr;
@@ -37,8 +38,9 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Plans: factor only; Q^T B only; R X = B only; and the whole least-squares
 // solve in one graph (factor, Q^T B and R X = B with the right-hand sides as
 // extra tile columns, so B's updates overlap the factorization).
-enum PlanKind { PK_FACTOR = 0, PK_APPLY = 1, PK_SOLVE = 2, PK_LSTSQ = 3, PK_SOLVET = 4 };
-bool solve_kind(int k) { return k == PK_SOLVE || k == PK_SOLVET; }
+// PK_SNE: R^T Z = B then R X = Z in one graph (semi-normal equations).
+enum PlanKind { PK_FACTOR = 0, PK_APPLY = 1, PK_SOLVE = 2, PK_LSTSQ = 3, PK_SOLVET = 4, PK_SNE = 5 };
+bool solve_kind(int k) { return k == PK_SOLVE || k == PK_SOLVET || k == PK_SNE; }
 
 struct PlanKey {
   int kind, p, q, nbcols, family, tree, param, stripes, stripes_b, priority;
@@ -87,8 +89,8 @@ std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
   spec.stripes_b = k.stripes_b;
   spec.panels = (k.kind == PK_FACTOR || k.kind == PK_LSTSQ);
   spec.b_updates = (k.kind == PK_APPLY || k.kind == PK_LSTSQ);
-  spec.solve = (k.kind == PK_SOLVE || k.kind == PK_LSTSQ);
-  spec.solve_t = (k.kind == PK_SOLVET);
+  spec.solve = (k.kind == PK_SOLVE || k.kind == PK_LSTSQ || k.kind == PK_SNE);
+  spec.solve_t = (k.kind == PK_SOLVET || k.kind == PK_SNE);
   std::vector<Elim> list;
   if (!solve_kind(k.kind)) list = make_list(k.tree, k.p, k.q, k.param);
   hp->g = build_graph(list, spec);
@@ -254,22 +256,26 @@ int run_plan(int kind, int64_t m, int64_t n, double *A, int64_t lda, double *B, 
   a.queue = reinterpret_cast<int32_t *>(st + align_up(sizeof(ExecCtl)));
   a.indeg = reinterpret_cast<int32_t *>(st + align_up(sizeof(ExecCtl)) +
                                         align_up((size_t)std::max<int32_t>(a.ntasks, 1) * 4));
-  a.A = A;
-  a.lda = lda;
-  a.m = m;
-  a.n = n;
-  a.B = B;
-  a.ldb = ldb;
-  a.nrhs = nrhs;
-  a.Tf = reinterpret_cast<double *>(base + kHeader);
-  a.p = (int)p;
-  a.q = (int)q;
+  a.prob.A = A;
+  a.prob.lda = lda;
+  a.prob.m = m;
+  a.prob.n = n;
+  a.prob.B = B;
+  a.prob.ldb = ldb;
+  a.prob.nrhs = nrhs;
+  a.prob.Tf = reinterpret_cast<double *>(base + kHeader);
+  a.prob.p = (int)p;
+  a.prob.q = (int)q;
+  a.prob.sw = nb / key.stripes;
+  a.prob.sw_b = nb / key.stripes_b;
+  a.prob.dma_ok = ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda % 2) == 0) ? 1 : 0;
+  a.prob.update_dtype = r.update_dtype;
+  a.prob.singular = &a.ctl->pad[0];
+  a.prob.skip = nullptr;
+  a.probs = nullptr;
+  a.nprob = 0;
   a.nb = nb;
   a.ib = r.ib;
-  a.sw = nb / key.stripes;
-  a.sw_b = nb / key.stripes_b;
-  a.dma_ok = ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda % 2) == 0) ? 1 : 0;
-  a.update_dtype = r.update_dtype;
   a.skip = skip;
   a.spin_limit = spin_limit_ticks(dev);
   a.trace = g_trace;
@@ -310,7 +316,7 @@ LsLayout ls_layout(int64_t m, int64_t n, int64_t nrhs, const Resolved &r) {
   if (mixed) {
     nt = std::max(nt, plan_tasks(PK_APPLY, m, n, nrhs, r));
     nt = std::max(nt, plan_tasks(PK_SOLVE, m, n, nrhs, r));
-    nt = std::max(nt, plan_tasks(PK_SOLVET, m, n, nrhs, r));
+    nt = std::max(nt, plan_tasks(PK_SNE, m, n, nrhs, r));
   }
   size_t off = 0;
   L.report = off;
@@ -334,6 +340,269 @@ LsLayout ls_layout(int64_t m, int64_t n, int64_t nrhs, const Resolved &r) {
   }
   L.total = off;
   return L;
+}
+
+
+// ------------------------------------------------------------- batches
+// A batch of least-squares problems runs as one task graph: the
+// concatenation of every problem's graph (tasks carry their problem index),
+// with one ready queue ordered by bottom level across problems, in one
+// executor launch.  Per-problem data (pointers, sizes, T factors) is in a
+// device table indexed by the task's problem.
+
+struct BatchKey {
+  int kind, nb, ib, family, stripes, priority;
+  int64_t nrhs;
+  std::vector<int32_t> shape;  // per problem: p, q, tree, param
+  bool operator<(const BatchKey &o) const {
+    return std::tie(kind, nb, ib, family, stripes, priority, nrhs, shape) <
+           std::tie(o.kind, o.nb, o.ib, o.family, o.stripes, o.priority, o.nrhs, o.shape);
+  }
+};
+
+struct BatchPlan {
+  DevicePlan d;
+  std::vector<int32_t> order;  // list order (sequential execution)
+  bool valid = false;
+};
+
+std::map<std::pair<int, BatchKey>, std::shared_ptr<BatchPlan>> g_batch;
+
+// Tree with the shortest tiled critical path for p x q tiles (the thesis's
+// own measure of a tree, section "Critical paths"), among the five trees.
+int auto_tree(int p, int q, int family) {
+  static std::map<std::tuple<int, int, int>, int> cache;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = cache.find({p, q, family});
+    if (it != cache.end()) return it->second;
+  }
+  const int cands[] = {TQR_GRASAP, TQR_GREEDY, TQR_FIBONACCI, TQR_BINARY, TQR_FLAT};
+  int best = TQR_GRASAP;
+  double bcp = 1e300;
+  for (int t : cands) {
+    GraphSpec spec;
+    spec.p = p;
+    spec.q = q;
+    spec.family = family;
+    const Graph g = build_graph(make_list(t, p, q, t == TQR_GRASAP ? 1 : 0), spec);
+    if (g.cp < bcp) {
+      bcp = g.cp;
+      best = t;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  cache[{p, q, family}] = best;
+  return best;
+}
+
+BatchKey batch_key(int kind, int count, const int64_t *m, const int64_t *n, int64_t nrhs, const Resolved &r,
+                   int tree_opt) {
+  BatchKey k{};
+  k.kind = kind;
+  k.nb = r.nb;
+  k.ib = r.ib;
+  k.family = solve_kind(kind) ? 0 : r.family;
+  k.stripes = r.stripes;
+  k.priority = r.priority;
+  k.nrhs = nrhs;
+  k.shape.reserve((size_t)count * 4);
+  for (int x = 0; x < count; x++) {
+    const int p = (int)cdiv(m[x], r.nb), q = (int)cdiv(n[x], r.nb);
+    int tree = tree_opt, param = r.param;
+    if (solve_kind(kind)) {
+      tree = 0;
+      param = 0;
+    } else if (tree_opt == TQR_AUTO) {
+      tree = auto_tree(p, q, r.family);
+      param = (tree == TQR_GRASAP) ? 1 : 0;
+    }
+    k.shape.insert(k.shape.end(), {p, q, tree, param});
+  }
+  return k;
+}
+
+std::shared_ptr<BatchPlan> batch_plan(const BatchKey &k, const Resolved &r, int dev) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_batch.find({dev, k});
+    if (it != g_batch.end()) return it->second;
+  }
+  auto bp = std::make_shared<BatchPlan>();
+  const int count = (int)(k.shape.size() / 4);
+  std::vector<Task> tasks;
+  std::vector<int32_t> off(1, 0), succ, indeg0;
+  std::vector<std::pair<double, int32_t>> ready;
+  bool valid = true;
+  for (int x = 0; x < count; x++) {
+    Resolved rx = r;
+    rx.tree = k.shape[4 * x + 2];
+    rx.param = k.shape[4 * x + 3];
+    auto hp = host_plan(make_key(k.kind, k.shape[4 * x], k.shape[4 * x + 1], k.kind == PK_FACTOR ? 0 : k.nrhs, rx));
+    valid = valid && hp->valid;
+    const Graph &g = hp->g;
+    const int32_t base = (int32_t)tasks.size();
+    for (size_t t = 0; t < g.tasks.size(); t++) {
+      Task tk = g.tasks[t];
+      tk.prob = x;
+      tasks.push_back(tk);
+      for (int32_t e = g.succ_off[t]; e < g.succ_off[t + 1]; e++) succ.push_back(base + g.succ[e]);
+      off.push_back((int32_t)succ.size());
+      indeg0.push_back(g.indeg0[t]);
+      bp->order.push_back(base + (int32_t)t);
+    }
+    for (int32_t t : g.ready0) ready.push_back({g.bottom[t], base + t});
+  }
+  std::stable_sort(ready.begin(), ready.end(),
+                   [](const std::pair<double, int32_t> &a, const std::pair<double, int32_t> &b) {
+                     return a.first > b.first;
+                   });
+  std::vector<int32_t> ready0;
+  for (auto &pr : ready) ready0.push_back(pr.second);
+  DevicePlan &d = bp->d;
+  if (upload(&d.tasks, tasks) != hipSuccess || upload(&d.succ_off, off) != hipSuccess ||
+      upload(&d.succ, succ) != hipSuccess || upload(&d.indeg0, indeg0) != hipSuccess ||
+      upload(&d.ready0, ready0) != hipSuccess)
+    valid = false;
+  d.ntasks = (int32_t)tasks.size();
+  d.nready0 = (int32_t)ready0.size();
+  bp->valid = valid;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_batch.find({dev, k});
+  if (it != g_batch.end()) return it->second;
+  g_batch[{dev, k}] = bp;
+  return bp;
+}
+
+// Pinned host staging for the per-call device tables: a ring of buffers per
+// device, each reused once the copy that read it last has completed.
+struct Staging {
+  void *host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+};
+constexpr int kStageRing = 4;
+std::map<int, std::pair<int, Staging[kStageRing]>> g_stage;
+
+int stage_copy(int dev, void *dst, const std::vector<char> &src, hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto &ring = g_stage[dev];
+  Staging &st = ring.second[ring.first];
+  ring.first = (ring.first + 1) % kStageRing;
+  if (st.done && hipEventSynchronize(st.done) != hipSuccess) return TQR_E_HIP;
+  if (st.bytes < src.size()) {
+    if (st.host) hipHostFree(st.host);
+    st.host = nullptr;
+    st.bytes = 0;
+    if (hipHostMalloc(&st.host, src.size(), hipHostMallocDefault) != hipSuccess) return TQR_E_NOMEM;
+    st.bytes = src.size();
+  }
+  if (!st.done && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) return TQR_E_HIP;
+  std::memcpy(st.host, src.data(), src.size());
+  if (hipMemcpyAsync(dst, st.host, src.size(), hipMemcpyHostToDevice, stream) != hipSuccess) return TQR_E_HIP;
+  if (hipEventRecord(st.done, stream) != hipSuccess) return TQR_E_HIP;
+  return TQR_OK;
+}
+
+// Workspace of tqr_lstsq_batched, all offsets 256-byte aligned:
+//   reports (count tqr_refine_report, contiguous), device tables (problem
+//   tables of the factor and refinement graphs, refinement table, copy
+//   descriptors, singular markers), executor state, then per problem: A's
+//   copy, B's copy, T factors and, with low-precision updates, the
+//   refinement buffers.
+struct BatchLayout {
+  size_t reports, tables, probs_f, probs_s, refs, copies, sing, state, state_bytes, total;
+  std::vector<size_t> ac, bc, tf, xw, rw, sw, part;
+  int64_t ntasks_f = 0, ntasks_s = 0;
+};
+
+BatchLayout batch_layout(int count, const int64_t *m, const int64_t *n, int64_t nrhs, const Resolved &r,
+                         const BatchKey &kf, const BatchKey &ks) {
+  BatchLayout L;
+  const bool mixed = r.update_dtype != TQR_F64;
+  for (int x = 0; x < count; x++) {
+    Resolved rx = r;
+    rx.tree = kf.shape[4 * x + 2];
+    rx.param = kf.shape[4 * x + 3];
+    L.ntasks_f += plan_tasks(PK_LSTSQ, m[x], n[x], nrhs, rx);
+    if (mixed) L.ntasks_s += plan_tasks(PK_SNE, m[x], n[x], nrhs, rx);
+  }
+  (void)ks;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  L.reports = take((size_t)count * sizeof(tqr_refine_report));
+  L.tables = off;
+  L.probs_f = take((size_t)count * sizeof(Problem));
+  L.probs_s = take((size_t)count * sizeof(Problem));
+  L.refs = take((size_t)count * sizeof(RefProb));
+  L.copies = take((size_t)count * 4 * sizeof(CopyDesc));  // in (A, B), mid, out
+  L.sing = take((size_t)count * sizeof(int32_t));
+  L.state_bytes = state_bytes(std::max(L.ntasks_f, L.ntasks_s));
+  L.state = take(L.state_bytes);
+  for (int x = 0; x < count; x++) {
+    L.ac.push_back(take((size_t)m[x] * n[x] * 8));
+    L.bc.push_back(take((size_t)m[x] * nrhs * 8));
+    L.tf.push_back(take(tfactor_bytes(cdiv(m[x], r.nb), cdiv(n[x], r.nb), r.nb, r.ib)));
+    if (mixed) {
+      L.xw.push_back(take((size_t)n[x] * nrhs * 8));
+      L.rw.push_back(take((size_t)m[x] * nrhs * 8));
+      L.sw.push_back(take((size_t)n[x] * nrhs * 8));
+      L.part.push_back(take(refine_partial_bytes(m[x], n[x], nrhs)));
+    }
+  }
+  L.total = off;
+  return L;
+}
+
+int check_batch(int count, const int64_t *m, const int64_t *n, int64_t nrhs) {
+  if (count < 1) return -1;
+  if (!m) return -2;
+  if (!n) return -3;
+  if (nrhs < 1) return -4;
+  for (int x = 0; x < count; x++)
+    if (m[x] < 1 || n[x] < 1 || n[x] > m[x]) return -2;
+  return TQR_OK;
+}
+
+int launch_batch(const BatchPlan &bp, const Resolved &r, int count, ExecCtl *ctl, const Problem *probs,
+                 int32_t *info, const int32_t *skip, int dev, hipStream_t stream, size_t state_bytes_) {
+  (void)state_bytes_;
+  ExecArgs a{};
+  a.tasks = bp.d.tasks;
+  a.succ_off = bp.d.succ_off;
+  a.succ = bp.d.succ;
+  a.indeg0 = bp.d.indeg0;
+  a.ready0 = bp.d.ready0;
+  a.ntasks = bp.d.ntasks;
+  a.nready0 = bp.d.nready0;
+  char *st = reinterpret_cast<char *>(ctl);
+  a.ctl = ctl;
+  a.queue = reinterpret_cast<int32_t *>(st + align_up(sizeof(ExecCtl)));
+  a.indeg = reinterpret_cast<int32_t *>(st + align_up(sizeof(ExecCtl)) +
+                                        align_up((size_t)std::max<int32_t>(a.ntasks, 1) * 4));
+  a.probs = probs;
+  a.nprob = count;
+  a.nb = r.nb;
+  a.ib = r.ib;
+  a.skip = skip;
+  a.spin_limit = spin_limit_ticks(dev);
+  a.trace = g_trace;
+  a.trace_cap = g_trace_cap;
+  const int grid = grid_size(dev, r.nb, r.ib);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (g_timing && hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess)
+    hipEventRecord(ev0, stream);
+  hipError_t e = launch_exec(a, r.exec == TQR_EXEC_SEQUENTIAL ? 1 : 0, grid, bp.order.data(), info, stream);
+  if (ev1) {
+    hipEventRecord(ev1, stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_events.emplace_back(ev0, ev1);
+  }
+  return e == hipSuccess ? TQR_OK : TQR_E_HIP;
 }
 
 }  // namespace
@@ -464,7 +733,11 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
     return TQR_E_HIP;
   if (hipMemcpy2DAsync(Bc, m * 8, B, ldb * 8, m * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return TQR_E_HIP;
-  if (refine_start(rep, stream) != hipSuccess) return TQR_E_HIP;
+  {
+    RefProb P0{};
+    P0.st = rep;
+    if (refine_start(nullptr, P0, 1, stream) != hipSuccess) return TQR_E_HIP;
+  }
   // factorization, Q^T B and R X = (Q^T B)(1:n) in one executor launch
   rc = run_plan(PK_LSTSQ, m, n, Ac, m, Bc, m, nrhs, T, L.t_bytes, r, info, stream);
   if (rc) return rc;
@@ -481,38 +754,279 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
   // the factorization error times r).  Every iteration is enqueued; the
   // kernels of the iterations after convergence return at once.
   const bool square = (m == n);
-  double *xw = reinterpret_cast<double *>(w + L.xw);
-  double *rw = reinterpret_cast<double *>(w + L.rw);
-  double *sw = reinterpret_cast<double *>(w + L.sw);
-  void *part = w + L.part;
+  RefProb P{};
+  P.A = A;
+  P.lda = lda;
+  P.m = m;
+  P.n = n;
+  P.B = B;
+  P.ldb = ldb;
+  P.nrhs = nrhs;
+  P.X = reinterpret_cast<double *>(w + L.xw);
+  P.ldx = n;
+  P.R = reinterpret_cast<double *>(w + L.rw);
+  P.ldr = m;
+  P.S = square ? nullptr : reinterpret_cast<double *>(w + L.sw);
+  P.lds = n;
+  P.partial = w + L.part;
+  P.st = rep;
+  P.info = info;
+  P.square = square ? 1 : 0;
   const double tol = r.refine_tol > 0.0 ? r.refine_tol : 16.0 * 2.220446049250313e-16;
   const int32_t *skip = &rep->done;
-  if (hipMemcpy2DAsync(xw, n * 8, Bc, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+  if (hipMemcpy2DAsync(P.X, n * 8, Bc, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return TQR_E_HIP;
-  if (refine_fro(A, lda, m, n, part, stream) != hipSuccess) return TQR_E_HIP;
+  if (refine_fro(nullptr, P, 1, stream) != hipSuccess) return TQR_E_HIP;
   for (int it = 0; it <= r.max_refine; it++) {
-    if (refine_residual(A, lda, m, n, xw, n, B, ldb, nrhs, rw, m, square ? nullptr : sw, n, part, rep,
-                        stream) != hipSuccess)
-      return TQR_E_HIP;
-    if (refine_check(m, n, nrhs, rw, m, square ? nullptr : sw, n, xw, n, B, ldb, part, tol, it, rep, stream) !=
-        hipSuccess)
-      return TQR_E_HIP;
+    if (refine_residual(nullptr, P, 1, m, n, stream) != hipSuccess) return TQR_E_HIP;
+    if (refine_check(nullptr, P, 1, tol, it, stream) != hipSuccess) return TQR_E_HIP;
     if (it == r.max_refine) break;
     if (square) {
-      rc = run_plan(PK_APPLY, m, n, Ac, m, rw, m, nrhs, T, L.t_bytes, r, info, stream, skip);
-      if (!rc) rc = run_plan(PK_SOLVE, m, n, Ac, m, rw, m, nrhs, T, L.t_bytes, r, info, stream, skip);
-      if (rc) return rc;
-      if (refine_update(n, nrhs, xw, n, rw, m, rep, stream) != hipSuccess) return TQR_E_HIP;
+      rc = run_plan(PK_APPLY, m, n, Ac, m, P.R, m, nrhs, T, L.t_bytes, r, info, stream, skip);
+      if (!rc) rc = run_plan(PK_SOLVE, m, n, Ac, m, P.R, m, nrhs, T, L.t_bytes, r, info, stream, skip);
     } else {
-      rc = run_plan(PK_SOLVET, m, n, Ac, m, sw, n, nrhs, T, L.t_bytes, r, info, stream, skip);
-      if (!rc) rc = run_plan(PK_SOLVE, m, n, Ac, m, sw, n, nrhs, T, L.t_bytes, r, info, stream, skip);
-      if (rc) return rc;
-      if (refine_update(n, nrhs, xw, n, sw, n, rep, stream) != hipSuccess) return TQR_E_HIP;
+      rc = run_plan(PK_SNE, m, n, Ac, m, P.S, n, nrhs, T, L.t_bytes, r, info, stream, skip);
     }
+    if (rc) return rc;
+    if (refine_update(nullptr, P, 1, n, nrhs, stream) != hipSuccess) return TQR_E_HIP;
   }
-  if (refine_finish(rep, info, TQR_INFO_NOCONV, stream) != hipSuccess) return TQR_E_HIP;
+  if (refine_finish(nullptr, P, 1, TQR_INFO_NOCONV, stream) != hipSuccess) return TQR_E_HIP;
+  double *xw = P.X;
   if (hipMemcpy2DAsync(X, ldx * 8, xw, n * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return TQR_E_HIP;
+  return TQR_OK;
+}
+
+size_t tqr_lstsq_batched_work_size(int32_t count, const int64_t *m, const int64_t *n, int64_t nrhs,
+                                   const tqr_opts *o) {
+  if (check_batch(count, m, n, nrhs)) return 0;
+  tqr_opts d;
+  tqr_default_opts(&d);
+  tqr_opts x = o ? *o : d;
+  int nbs[16], ibs[16];
+  int nc = 1;
+  if (x.nb == 0) {
+    nc = std::min(config_list(nbs, ibs, 16), 16);
+  } else {
+    nbs[0] = x.nb;
+    ibs[0] = x.ib;
+  }
+  size_t best = 0;
+  for (int c = 0; c < nc; c++) {
+    x.nb = nbs[c];
+    x.ib = ibs[c];
+    Resolved r;
+    if (resolve(&x, &r)) return 0;
+    const BatchKey kf = batch_key(PK_LSTSQ, count, m, n, nrhs, r, x.tree);
+    const BatchKey ks = batch_key(PK_SNE, count, m, n, nrhs, r, x.tree);
+    best = std::max(best, batch_layout(count, m, n, nrhs, r, kf, ks).total);
+  }
+  return best;
+}
+
+int tqr_lstsq_batched(int32_t count, const int64_t *m, const int64_t *n, int64_t nrhs, const double *const *A,
+                      const int64_t *lda, const double *const *B, const int64_t *ldb, double *const *X,
+                      const int64_t *ldx, void *work, size_t work_bytes, const tqr_opts *o, int32_t *info,
+                      hipStream_t stream) {
+  int rc = check_batch(count, m, n, nrhs);
+  if (rc) return rc;
+  if (!A || !lda || !B || !ldb || !X || !ldx) return -5;
+  for (int x = 0; x < count; x++) {
+    if (!A[x] || lda[x] < m[x]) return -5;
+    if (!B[x] || ldb[x] < m[x]) return -7;
+    if (!X[x] || ldx[x] < n[x]) return -9;
+  }
+  if (!work) return -11;
+  tqr_opts d;
+  tqr_default_opts(&d);
+  const int tree_opt = o ? o->tree : d.tree;
+  Resolved r;
+  rc = resolve(o, &r);
+  if (rc) return rc;
+  const bool mixed = r.update_dtype != TQR_F64;
+  const BatchKey kf = batch_key(PK_LSTSQ, count, m, n, nrhs, r, tree_opt);
+  const BatchKey ks = batch_key(PK_SNE, count, m, n, nrhs, r, tree_opt);
+  const BatchLayout L = batch_layout(count, m, n, nrhs, r, kf, ks);
+  if (work_bytes < L.total) return TQR_E_WORKSPACE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TQR_E_HIP;
+  auto bpf = batch_plan(kf, r, dev);
+  if (!bpf->valid) return TQR_E_INTERNAL;
+  std::shared_ptr<BatchPlan> bps;
+  if (mixed) {
+    bps = batch_plan(ks, r, dev);
+    if (!bps->valid) return TQR_E_INTERNAL;
+  }
+  char *w = static_cast<char *>(work);
+  auto *reports = reinterpret_cast<RefineState *>(w + L.reports);
+  auto *sing = reinterpret_cast<int32_t *>(w + L.sing);
+  // device tables, staged in one copy
+  std::vector<char> tab(L.state - L.tables, 0);
+  auto at = [&](size_t off) { return tab.data() + (off - L.tables); };
+  auto *pf = reinterpret_cast<Problem *>(at(L.probs_f));
+  auto *ps = reinterpret_cast<Problem *>(at(L.probs_s));
+  auto *rf = reinterpret_cast<RefProb *>(at(L.refs));
+  auto *cp = reinterpret_cast<CopyDesc *>(at(L.copies));
+  int64_t mmax = 0, nmax = 0, emax = 0;
+  for (int x = 0; x < count; x++) {
+    double *Ac = reinterpret_cast<double *>(w + L.ac[x]);
+    double *Bc = reinterpret_cast<double *>(w + L.bc[x]);
+    const int stripes_b = (nrhs <= r.nb / r.stripes) ? 1 : r.stripes;
+    Problem P{};
+    P.A = Ac;
+    P.lda = m[x];
+    P.m = m[x];
+    P.n = n[x];
+    P.B = Bc;
+    P.ldb = m[x];
+    P.nrhs = nrhs;
+    P.Tf = reinterpret_cast<double *>(w + L.tf[x]);
+    P.p = (int)cdiv(m[x], r.nb);
+    P.q = (int)cdiv(n[x], r.nb);
+    P.sw = r.nb / r.stripes;
+    P.sw_b = r.nb / stripes_b;
+    P.dma_ok = (m[x] % 2 == 0) ? 1 : 0;
+    P.update_dtype = r.update_dtype;
+    P.singular = sing + x;
+    P.skip = nullptr;
+    pf[x] = P;
+    cp[2 * x] = CopyDesc{A[x], lda[x], Ac, m[x], m[x], n[x]};
+    cp[2 * x + 1] = CopyDesc{B[x], ldb[x], Bc, m[x], m[x], nrhs};
+    mmax = std::max(mmax, m[x]);
+    nmax = std::max(nmax, n[x]);
+    emax = std::max(emax, m[x] * std::max(n[x], nrhs));
+    RefProb R{};
+    R.st = reports + x;
+    R.info = info ? info + x : nullptr;
+    if (mixed) {
+      double *sw = reinterpret_cast<double *>(w + L.sw[x]);
+      Problem Q = P;
+      Q.B = sw;
+      Q.ldb = n[x];
+      Q.skip = &reports[x].done;
+      ps[x] = Q;
+      R.A = A[x];
+      R.lda = lda[x];
+      R.m = m[x];
+      R.n = n[x];
+      R.B = B[x];
+      R.ldb = ldb[x];
+      R.nrhs = nrhs;
+      R.X = reinterpret_cast<double *>(w + L.xw[x]);
+      R.ldx = n[x];
+      R.R = reinterpret_cast<double *>(w + L.rw[x]);
+      R.ldr = m[x];
+      R.S = sw;
+      R.lds = n[x];
+      R.partial = w + L.part[x];
+      R.square = 0;  // batched refinement: semi-normal equations for every problem
+    }
+    rf[x] = R;
+  }
+  // result copies: X = first n rows of the solved B copies (of the refined
+  // iterate with low-precision updates); with refinement the iterate starts
+  // from the solved B copies
+  for (int x = 0; x < count; x++) {
+    double *bc = reinterpret_cast<double *>(w + L.bc[x]);
+    if (mixed) {
+      double *xw = reinterpret_cast<double *>(w + L.xw[x]);
+      cp[2 * count + x] = CopyDesc{bc, m[x], xw, n[x], n[x], nrhs};
+      cp[3 * count + x] = CopyDesc{xw, n[x], X[x], ldx[x], n[x], nrhs};
+    } else {
+      cp[3 * count + x] = CopyDesc{bc, m[x], X[x], ldx[x], n[x], nrhs};
+    }
+  }
+  rc = stage_copy(dev, w + L.tables, tab, stream);
+  if (rc) return rc;
+  const RefProb none{};
+  const auto *dref = reinterpret_cast<const RefProb *>(w + L.refs);
+  const auto *dcp = reinterpret_cast<const CopyDesc *>(w + L.copies);
+  if (copy_batch(dcp, 2 * count, emax, stream) != hipSuccess) return TQR_E_HIP;
+  if (refine_start(dref, none, count, stream) != hipSuccess) return TQR_E_HIP;
+  auto *ctl = reinterpret_cast<ExecCtl *>(w + L.state);
+  rc = launch_batch(*bpf, r, count, ctl, reinterpret_cast<const Problem *>(w + L.probs_f), info, nullptr, dev,
+                    stream, L.state_bytes);
+  if (rc) return rc;
+  if (mixed) {
+    if (copy_batch(dcp + 2 * count, count, nmax * nrhs, stream) != hipSuccess) return TQR_E_HIP;
+    const double tol = r.refine_tol > 0.0 ? r.refine_tol : 16.0 * 2.220446049250313e-16;
+    if (refine_fro(dref, none, count, stream) != hipSuccess) return TQR_E_HIP;
+    for (int it = 0; it <= r.max_refine; it++) {
+      if (refine_residual(dref, none, count, mmax, nmax, stream) != hipSuccess) return TQR_E_HIP;
+      if (refine_check(dref, none, count, tol, it, stream) != hipSuccess) return TQR_E_HIP;
+      if (it == r.max_refine) break;
+      rc = launch_batch(*bps, r, count, ctl, reinterpret_cast<const Problem *>(w + L.probs_s), info, nullptr,
+                        dev, stream, L.state_bytes);
+      if (rc) return rc;
+      if (refine_update(dref, none, count, nmax, nrhs, stream) != hipSuccess) return TQR_E_HIP;
+    }
+    if (refine_finish(dref, none, count, TQR_INFO_NOCONV, stream) != hipSuccess) return TQR_E_HIP;
+  }
+  if (copy_batch(dcp + 3 * count, count, nmax * nrhs, stream) != hipSuccess) return TQR_E_HIP;
+  return TQR_OK;
+}
+
+int tqr_autotune_batched(int32_t count, const int64_t *m, const int64_t *n, int64_t nrhs, const double *const *A,
+                         const int64_t *lda, const double *const *B, const int64_t *ldb, double *const *X,
+                         const int64_t *ldx, void *work, size_t work_bytes, tqr_opts *o, float *best_ms,
+                         hipStream_t stream) {
+  if (!o) return -13;
+  int rc = check_batch(count, m, n, nrhs);
+  if (rc) return rc;
+  static std::map<std::vector<int64_t>, std::pair<int, int>> cache;
+  std::vector<int64_t> sig = {count, nrhs, o->tree, o->kernels, o->update_dtype, o->param, o->stripes};
+  for (int x = 0; x < count; x++) {
+    sig.push_back(m[x]);
+    sig.push_back(n[x]);
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = cache.find(sig);
+    if (it != cache.end()) {
+      o->nb = it->second.first;
+      o->ib = it->second.second;
+      if (best_ms) *best_ms = -1.0f;
+      return TQR_OK;
+    }
+  }
+  int nbs[16], ibs[16];
+  const int nc = std::min(config_list(nbs, ibs, 16), 16);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TQR_E_HIP;
+  float bms = 1e30f;
+  int bnb = 0, bib = 0;
+  for (int c = 0; c < nc; c++) {
+    tqr_opts x = *o;
+    x.nb = nbs[c];
+    x.ib = ibs[c];
+    // first run builds and uploads the plans; the second is timed
+    rc = tqr_lstsq_batched(count, m, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, &x, nullptr, stream);
+    if (rc == TQR_E_WORKSPACE) continue;
+    if (rc) break;
+    hipEventRecord(e0, stream);
+    rc = tqr_lstsq_batched(count, m, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, &x, nullptr, stream);
+    hipEventRecord(e1, stream);
+    if (rc) break;
+    float ms = 0.0f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = TQR_E_HIP;
+      break;
+    }
+    if (ms < bms) {
+      bms = ms;
+      bnb = x.nb;
+      bib = x.ib;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  if (bnb == 0) return TQR_E_WORKSPACE;
+  o->nb = bnb;
+  o->ib = bib;
+  if (best_ms) *best_ms = bms;
+  std::lock_guard<std::mutex> lk(g_mu);
+  cache[sig] = {bnb, bib};
   return TQR_OK;
 }
 
@@ -596,7 +1110,7 @@ void tqr_debug_trace(int64_t *buf, int64_t cap) {
 int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *tasks,
                     int64_t cap) {
   if (m < 1 || n < 1 || n > m) return -1;
-  if (kind < PK_FACTOR || kind > PK_SOLVET) return -4;
+  if (kind < PK_FACTOR || kind > PK_SNE) return -4;
   Resolved r;
   int rc = resolve(o, &r);
   if (rc) return rc;
@@ -621,7 +1135,7 @@ int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_
 int tqr_debug_succ(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *off,
                    int32_t *succ, int64_t cap) {
   if (m < 1 || n < 1 || n > m) return -1;
-  if (kind < PK_FACTOR || kind > PK_SOLVET) return -4;
+  if (kind < PK_FACTOR || kind > PK_SNE) return -4;
   Resolved r;
   int rc = resolve(o, &r);
   if (rc) return rc;

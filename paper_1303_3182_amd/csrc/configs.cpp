@@ -49,6 +49,19 @@ bool config_supported(int nb, int ib) {
   return false;
 }
 
+int config_list(int *nb, int *ib, int cap) {
+  int k = 0;
+#define X(NB, IB)     \
+  if (k < cap) {      \
+    nb[k] = NB;       \
+    ib[k] = IB;       \
+  }                   \
+  k++;
+  TQR_CONFIGS(X)
+#undef X
+  return k;
+}
+
 int chunk_width(int nb, int ib) {
   (void)ib;
   return nb < 64 ? nb : 64;

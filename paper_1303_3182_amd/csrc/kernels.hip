@@ -1147,7 +1147,8 @@ __device__ __forceinline__ void trsmt_waves(const double *R, int64_t ldr, int nk
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
 template <int NB, int IB, int WC>
-__device__ __forceinline__ void run_task(const ExecArgs &a, const Task &t, Smem<NB, IB, WC> &sm) {
+__device__ __forceinline__ void run_task(const Problem &a, const Task &t, Smem<NB, IB, WC> &sm) {
+  if (a.skip && *a.skip) return;
   const int64_t lda = a.lda;
   auto tileA = [&](int i, int j) { return a.A + (int64_t)j * NB * lda + (int64_t)i * NB; };
   auto rowsOf = [&](int i) { return (int)min((int64_t)NB, a.m - (int64_t)i * NB); };
@@ -1180,13 +1181,13 @@ __device__ __forceinline__ void run_task(const ExecArgs &a, const Task &t, Smem<
       const int nc = imin(WC, cend - cs);
       if (kind == K_TRSM && nc <= 2 * (NT / 64))
         trsm_waves<NB, IB, WC>(tileA(t.k, t.k), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
-                               a.ldb, nc, t.k * NB, &a.ctl->pad[0], sm);
+                               a.ldb, nc, t.k * NB, a.singular, sm);
       else if (kind == K_TRSM)
         trsm_tile<NB, IB, WC>(tileA(t.k, t.k), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
-                              a.ldb, nc, t.k * NB, &a.ctl->pad[0], sm);
+                              a.ldb, nc, t.k * NB, a.singular, sm);
       else if (kind == K_TRSMT)
         trsmt_waves<NB, IB, WC>(tileA(t.k, t.k), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
-                                a.ldb, nc, t.k * NB, &a.ctl->pad[0], sm);
+                                a.ldb, nc, t.k * NB, a.singular, sm);
       else if (kind == K_GEMM)
         gemm_tile<NB, IB, WC>(tileA(t.i, t.k), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
                               a.ldb, Bc + (int64_t)cs * a.ldb + (int64_t)t.i * NB, a.ldb, NB, nc, false, sm);
@@ -1272,6 +1273,7 @@ __device__ __forceinline__ Task load_task(const Task *p) {
   t.k = __builtin_amdgcn_readfirstlane(t.k);
   t.j = __builtin_amdgcn_readfirstlane(t.j);
   t.stripe = __builtin_amdgcn_readfirstlane(t.stripe);
+  t.prob = __builtin_amdgcn_readfirstlane(t.prob);
   return t;
 }
 
@@ -1297,6 +1299,9 @@ __global__ void exec_reset(ExecArgs a) {
     a.indeg[x] = a.indeg0[x];
     a.queue[x] = (x < a.nready0) ? a.ready0[x] : -1;
   }
+  if (a.probs)
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < a.nprob; x += stride)
+      *a.probs[x].singular = 0x7fffffff;
   if (blockIdx.x == 0 && threadIdx.x < 16) {
     int32_t *c = reinterpret_cast<int32_t *>(a.ctl);
     c[threadIdx.x] = 0;
@@ -1344,7 +1349,10 @@ __global__ __launch_bounds__(NT, 1) void exec_persistent(ExecArgs a) {
     if (tid < 0) break;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int64_t tstart = a.trace ? (int64_t)wall_clock64() : 0;
-    run_task<NB, IB, WC>(a, load_task(a.tasks + tid), sm);
+    {
+      const Task t = load_task(a.tasks + tid);
+      run_task<NB, IB, WC>(a.probs ? a.probs[t.prob] : a.prob, t, sm);
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1374,7 +1382,10 @@ __global__ __launch_bounds__(NT, 1) void exec_one(ExecArgs a, int tid) {
   __shared__ Smem<NB, IB, WC> sm;
   if (a.skip && *a.skip) return;
   const int64_t tstart = a.trace ? (int64_t)wall_clock64() : 0;
-  run_task<NB, IB, WC>(a, load_task(a.tasks + tid), sm);
+  {
+    const Task t = load_task(a.tasks + tid);
+    run_task<NB, IB, WC>(a.probs ? a.probs[t.prob] : a.prob, t, sm);
+  }
   __syncthreads();
   if (a.trace && threadIdx.x == 0 && tid < a.trace_cap) {
     int64_t *tr = a.trace + 4 * (int64_t)tid;
@@ -1388,9 +1399,16 @@ __global__ __launch_bounds__(NT, 1) void exec_one(ExecArgs a, int tid) {
 template <int NB>
 __global__ void exec_finish(ExecArgs a, int32_t *info) {
   if (a.skip && *a.skip) return;
+  const int e = a.ctl->error;
+  if (a.probs) {  // one info entry per problem
+    for (int x = threadIdx.x; x < a.nprob; x += blockDim.x) {
+      const int z = *a.probs[x].singular;
+      if (info) info[x] = (e != 0) ? e : (z != 0x7fffffff ? z : 0);
+    }
+    return;
+  }
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const int e = a.ctl->error;
-    const int z = a.ctl->pad[0];
+    const int z = *a.prob.singular;
     if (info) *info = (e != 0) ? e : (z != 0x7fffffff ? z : 0);
   }
 }

@@ -1,5 +1,6 @@
 // Refinement kernels (refine.hip): FP64 residuals with compensated dot
-// products, the backward-error stopping test and the correction update.
+// products, the backward-error stopping test and the correction update, for
+// one problem or a batch; plus batched column-major copies.
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
@@ -16,19 +17,47 @@ constexpr int kFroBlocks = 256;  // partial sums of ||A||_F^2
 // Device-resident state of one refinement, laid out as tqr_refine_report.
 typedef tqr_refine_report RefineState;
 
+// One problem of a refinement: the caller's A and B, the iterate X (n x
+// nrhs), the residual R (m x nrhs; for square problems also the correction,
+// in place), A^T R and then the correction S (n x nrhs, rectangular only),
+// scratch of refine_partial_bytes, the state and an optional info word.
+struct RefProb {
+  const double *A;
+  int64_t lda, m, n;
+  const double *B;
+  int64_t ldb, nrhs;
+  double *X;
+  int64_t ldx;
+  double *R;
+  int64_t ldr;
+  double *S;
+  int64_t lds;
+  void *partial;
+  RefineState *st;
+  int32_t *info;
+  int32_t square;
+  int32_t pad_;
+};
+
+struct CopyDesc {
+  const double *src;
+  int64_t lds;
+  double *dst;
+  int64_t ldd;
+  int64_t rows, cols;
+};
+
 size_t refine_partial_bytes(int64_t m, int64_t n, int64_t nrhs);
-hipError_t refine_start(RefineState *st, hipStream_t s);
-hipError_t refine_fro(const double *A, int64_t lda, int64_t m, int64_t n, void *partial, hipStream_t s);
-// R = B - A X (m x nrhs); if S is not null, also S = A^T R (n x nrhs).
-hipError_t refine_residual(const double *A, int64_t lda, int64_t m, int64_t n, const double *X, int64_t ldx,
-                           const double *B, int64_t ldb, int64_t nrhs, double *R, int64_t ldr, double *S,
-                           int64_t lds, void *partial, const RefineState *st, hipStream_t s);
-// Backward error of the current X (square when S is null); sets done when <= tol.
-hipError_t refine_check(int64_t m, int64_t n, int64_t nrhs, const double *R, int64_t ldr, const double *S,
-                        int64_t lds, const double *X, int64_t ldx, const double *B, int64_t ldb,
-                        const void *partial, double tol, int it, RefineState *st, hipStream_t s);
-hipError_t refine_update(int64_t n, int64_t nrhs, double *X, int64_t ldx, const double *D, int64_t ldd,
-                         const RefineState *st, hipStream_t s);
-hipError_t refine_finish(const RefineState *st, int32_t *info, int32_t noconv, hipStream_t s);
+// `tab` null: the single problem `one` (count 1); else a device table of
+// `count` problems with largest sizes mmax x nmax.
+hipError_t refine_start(const RefProb *tab, const RefProb &one, int count, hipStream_t s);
+hipError_t refine_fro(const RefProb *tab, const RefProb &one, int count, hipStream_t s);
+hipError_t refine_residual(const RefProb *tab, const RefProb &one, int count, int64_t mmax, int64_t nmax,
+                           hipStream_t s);
+hipError_t refine_check(const RefProb *tab, const RefProb &one, int count, double tol, int it, hipStream_t s);
+hipError_t refine_update(const RefProb *tab, const RefProb &one, int count, int64_t nmax, int64_t nrhs,
+                         hipStream_t s);
+hipError_t refine_finish(const RefProb *tab, const RefProb &one, int count, int32_t noconv, hipStream_t s);
+hipError_t copy_batch(const CopyDesc *tab, int count, int64_t max_elems, hipStream_t s);
 
 }  // namespace tqr

@@ -5,6 +5,9 @@
 // refinement's `done` flag and returns at once when it is set, so that a
 // fixed number of iterations can be enqueued without host round trips.
 //
+// Each kernel serves one problem (passed by value) or a batch (a device
+// table, one problem per blockIdx.z).
+//
 // Compensated dot product (Ogita, Rump and Oishi, "Accurate sum and dot
 // product", SIAM J. Sci. Comput. 26, 2005, algorithm Dot2): each product is
 // split exactly with an FMA (a*b = p + e), each sum exactly with Knuth's
@@ -49,9 +52,7 @@ __device__ __forceinline__ dd dd_add(dd x, dd y) {
   return dd{s, e + x.lo + y.lo};
 }
 
-__device__ __forceinline__ double shfl_xor_d(double v, int m) {
-  return __shfl_xor(v, m, 64);
-}
+__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
 
 __device__ __forceinline__ dd wave_sum_dd(dd v) {
 #pragma unroll
@@ -75,186 +76,213 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return t;
 }
 
-// partial[(z * nch + y) * m + i] = sum over columns j of chunk y of A(i, j) x(j, z)
-__global__ __launch_bounds__(RT) void resid_partial(const double *A, int64_t lda, int64_t m, int64_t n,
-                                                    const double *X, int64_t ldx, dd *partial,
-                                                    const RefineState *st) {
-  if (st->done) return;
+__device__ __forceinline__ const RefProb &pick(const RefProb *tab, const RefProb &one) {
+  return tab ? tab[blockIdx.z] : one;
+}
+
+__device__ __forceinline__ double *fro_of(const RefProb &P) { return static_cast<double *>(P.partial); }
+__device__ __forceinline__ dd *part_of(const RefProb &P) {
+  return reinterpret_cast<dd *>(static_cast<char *>(P.partial) + (size_t)kFroBlocks * sizeof(double));
+}
+
+// partial[(z * nch + y) * m + i] = sum over columns j of chunk y of A(i, j) X(j, z)
+__global__ __launch_bounds__(RT) void resid_partial(const RefProb *tab, RefProb one) {
+  const RefProb &P = pick(tab, one);
+  if (P.st->done) return;
+  const int64_t nch = (P.n + RCHUNK - 1) / RCHUNK;
+  const int64_t y = blockIdx.y;
+  if (y >= nch || (int64_t)blockIdx.x * RT >= P.m) return;
   const int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x;
-  const int64_t y = blockIdx.y, z = blockIdx.z;
-  const int64_t nch = gridDim.y;
-  const int64_t j0 = y * RCHUNK, j1 = min(n, j0 + RCHUNK);
+  const int64_t j0 = y * RCHUNK, j1 = min(P.n, j0 + RCHUNK);
   __shared__ double xs[RCHUNK];
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += RT) xs[j - j0] = X[z * ldx + j];
-  __syncthreads();
-  if (i >= m) return;
-  dd acc{0.0, 0.0};
-  for (int64_t j = j0; j < j1; j++) dot2_step(acc, A[j * lda + i], xs[j - j0]);
-  partial[(z * nch + y) * m + i] = acc;
+  for (int64_t z = 0; z < P.nrhs; z++) {
+    __syncthreads();
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += RT) xs[j - j0] = P.X[z * P.ldx + j];
+    __syncthreads();
+    if (i < P.m) {
+      dd acc{0.0, 0.0};
+      for (int64_t j = j0; j < j1; j++) dot2_step(acc, P.A[j * P.lda + i], xs[j - j0]);
+      part_of(P)[(z * nch + y) * P.m + i] = acc;
+    }
+  }
 }
 
 // R(i, z) = B(i, z) - sum_y partial  (compensated over the chunks)
-__global__ __launch_bounds__(RT) void resid_reduce(int64_t m, int nch, const dd *partial, const double *B,
-                                                   int64_t ldb, double *R, int64_t ldr,
-                                                   const RefineState *st) {
-  if (st->done) return;
+__global__ __launch_bounds__(RT) void resid_reduce(const RefProb *tab, RefProb one) {
+  const RefProb &P = pick(tab, one);
+  if (P.st->done) return;
   const int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x;
-  const int64_t z = blockIdx.y;
-  if (i >= m) return;
-  dd acc{B[z * ldb + i], 0.0};
-  for (int y = 0; y < nch; y++) {
-    const dd p = partial[(z * nch + y) * m + i];
-    acc = dd_add(acc, dd{-p.hi, -p.lo});
+  if (i >= P.m) return;
+  const int64_t nch = (P.n + RCHUNK - 1) / RCHUNK;
+  const dd *part = part_of(P);
+  for (int64_t z = 0; z < P.nrhs; z++) {
+    dd acc{P.B[z * P.ldb + i], 0.0};
+    for (int64_t y = 0; y < nch; y++) {
+      const dd p = part[(z * nch + y) * P.m + i];
+      acc = dd_add(acc, dd{-p.hi, -p.lo});
+    }
+    P.R[z * P.ldr + i] = acc.hi + acc.lo;
   }
-  R[z * ldr + i] = acc.hi + acc.lo;
 }
 
-// S(j, z) = sum_i A(i, j) R(i, z): one wave per (column j, right-hand side z)
-__global__ __launch_bounds__(RT) void atr(const double *A, int64_t lda, int64_t m, int64_t n,
-                                          const double *R, int64_t ldr, double *S, int64_t lds,
-                                          const RefineState *st) {
-  if (st->done) return;
+// S(j, z) = sum_i A(i, j) R(i, z): one wave per column j
+__global__ __launch_bounds__(RT) void atr(const RefProb *tab, RefProb one) {
+  const RefProb &P = pick(tab, one);
+  if (P.st->done || !P.S) return;
   const int64_t j = (int64_t)blockIdx.x * (RT / 64) + (threadIdx.x >> 6);
-  const int64_t z = blockIdx.y;
   const int lane = threadIdx.x & 63;
-  if (j >= n) return;  // whole waves leave together
-  dd acc{0.0, 0.0};
-  for (int64_t i = lane; i < m; i += 64) dot2_step(acc, A[j * lda + i], R[z * ldr + i]);
-  acc = wave_sum_dd(acc);
-  if (lane == 0) S[z * lds + j] = acc.hi + acc.lo;
+  if (j >= P.n) return;  // whole waves leave together
+  for (int64_t z = 0; z < P.nrhs; z++) {
+    dd acc{0.0, 0.0};
+    for (int64_t i = lane; i < P.m; i += 64) dot2_step(acc, P.A[j * P.lda + i], P.R[z * P.ldr + i]);
+    acc = wave_sum_dd(acc);
+    if (lane == 0) P.S[z * P.lds + j] = acc.hi + acc.lo;
+  }
 }
 
 // Squares of A's entries, per block of columns, for ||A||_F.
-__global__ __launch_bounds__(RT) void fro_partial(const double *A, int64_t lda, int64_t m, int64_t n,
-                                                  double *out) {
+__global__ __launch_bounds__(RT) void fro_partial(const RefProb *tab, RefProb one) {
+  const RefProb &P = pick(tab, one);
   __shared__ double red[RT / 64];
   double s = 0.0;
-  for (int64_t j = blockIdx.x; j < n; j += gridDim.x)
-    for (int64_t i = threadIdx.x; i < m; i += RT) {
-      const double v = A[j * lda + i];
+  for (int64_t j = blockIdx.x; j < P.n; j += gridDim.x)
+    for (int64_t i = threadIdx.x; i < P.m; i += RT) {
+      const double v = P.A[j * P.lda + i];
       s = fma(v, v, s);
     }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) out[blockIdx.x] = s;
+  if (threadIdx.x == 0) fro_of(P)[blockIdx.x] = s;
 }
 
 // Stopping test of iteration `it`.  Square problems: normwise backward
 // error ||r|| / (||A||_F ||x|| + ||b||) (Rigal and Gaches); rectangular
 // ones: ||A^T r|| / (||A||_F ||r||), Stewart's bound on the backward error
 // of a least-squares solution.  The test passes when every right-hand side
-// meets tol; `done` then stops every later kernel.
-__global__ __launch_bounds__(RT) void check(int64_t m, int64_t n, int64_t nrhs, const double *R, int64_t ldr,
-                                            const double *S, int64_t lds, const double *X, int64_t ldx,
-                                            const double *B, int64_t ldb, const double *fro, int nfro,
-                                            double tol, int square, int it, RefineState *st) {
-  if (st->done) return;
+// meets tol; `done` then stops every later kernel of this problem.
+__global__ __launch_bounds__(RT) void check(const RefProb *tab, RefProb one, double tol, int it) {
+  const RefProb &P = pick(tab, one);
+  if (P.st->done) return;
   __shared__ double red[RT / 64];
   double f = 0.0;
-  for (int i = threadIdx.x; i < nfro; i += RT) f += fro[i];
+  for (int i = threadIdx.x; i < kFroBlocks; i += RT) f += fro_of(P)[i];
   const double anorm = sqrt(block_sum(f, red));
   double worst = 0.0;
-  for (int64_t z = 0; z < nrhs; z++) {
+  for (int64_t z = 0; z < P.nrhs; z++) {
     double rr = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += RT) rr = fma(R[z * ldr + i], R[z * ldr + i], rr);
+    for (int64_t i = threadIdx.x; i < P.m; i += RT) rr = fma(P.R[z * P.ldr + i], P.R[z * P.ldr + i], rr);
     const double rn = sqrt(block_sum(rr, red));
     double be;
-    if (square) {
+    if (P.square) {
       double xx = 0.0, bb = 0.0;
-      for (int64_t i = threadIdx.x; i < n; i += RT) xx = fma(X[z * ldx + i], X[z * ldx + i], xx);
-      for (int64_t i = threadIdx.x; i < m; i += RT) bb = fma(B[z * ldb + i], B[z * ldb + i], bb);
+      for (int64_t i = threadIdx.x; i < P.n; i += RT) xx = fma(P.X[z * P.ldx + i], P.X[z * P.ldx + i], xx);
+      for (int64_t i = threadIdx.x; i < P.m; i += RT) bb = fma(P.B[z * P.ldb + i], P.B[z * P.ldb + i], bb);
       const double xn = sqrt(block_sum(xx, red)), bn = sqrt(block_sum(bb, red));
       be = rn / (anorm * xn + bn);
     } else {
       double ss = 0.0;
-      for (int64_t i = threadIdx.x; i < n; i += RT) ss = fma(S[z * lds + i], S[z * lds + i], ss);
+      for (int64_t i = threadIdx.x; i < P.n; i += RT) ss = fma(P.S[z * P.lds + i], P.S[z * P.lds + i], ss);
       const double sn = sqrt(block_sum(ss, red));
       be = (rn == 0.0) ? 0.0 : sn / (anorm * rn);
     }
     worst = fmax(worst, be);
   }
   if (threadIdx.x == 0) {
-    st->backward_error = worst;
-    if (it < kRefineHistory) st->history[it] = worst;
-    st->iterations = it;
-    if (worst <= tol) st->done = 1;
+    P.st->backward_error = worst;
+    if (it < kRefineHistory) P.st->history[it] = worst;
+    P.st->iterations = it;
+    if (worst <= tol) P.st->done = 1;
   }
 }
 
-// X += D
-__global__ __launch_bounds__(RT) void update(int64_t n, int64_t nrhs, double *X, int64_t ldx, const double *D,
-                                             int64_t ldd, const RefineState *st) {
-  if (st->done) return;
+// X += D (D = S for rectangular problems, the first n rows of R for square ones)
+__global__ __launch_bounds__(RT) void update(const RefProb *tab, RefProb one) {
+  const RefProb &P = pick(tab, one);
+  if (P.st->done) return;
   const int64_t k = (int64_t)blockIdx.x * RT + threadIdx.x;
-  if (k >= n * nrhs) return;
-  const int64_t z = k / n, i = k % n;
-  X[z * ldx + i] += D[z * ldd + i];
+  if (k >= P.n * P.nrhs) return;
+  const int64_t z = k / P.n, i = k % P.n;
+  const double d = P.square ? P.R[z * P.ldr + i] : P.S[z * P.lds + i];
+  P.X[z * P.ldx + i] += d;
 }
 
-__global__ void start(RefineState *st) {
-  if (threadIdx.x == 0) {
-    st->done = 0;
-    st->iterations = 0;
-    st->backward_error = -1.0;
-    for (int i = 0; i < kRefineHistory; i++) st->history[i] = -1.0;
+__global__ void start(const RefProb *tab, RefProb one, int count) {
+  for (int x = threadIdx.x; x < count; x += blockDim.x) {
+    const RefProb &P = tab ? tab[x] : one;
+    P.st->done = 0;
+    P.st->iterations = 0;
+    P.st->backward_error = -1.0;
+    for (int i = 0; i < kRefineHistory; i++) P.st->history[i] = -1.0;
   }
 }
 
-__global__ void finish(const RefineState *st, int32_t *info, int32_t noconv) {
-  if (threadIdx.x == 0 && info && !st->done && *info == 0) *info = noconv;
+__global__ void finish(const RefProb *tab, RefProb one, int count, int32_t noconv) {
+  for (int x = threadIdx.x; x < count; x += blockDim.x) {
+    const RefProb &P = tab ? tab[x] : one;
+    if (P.info && !P.st->done && *P.info == 0) *P.info = noconv;
+  }
 }
+
+// Column-major block copies, one per blockIdx.z.
+__global__ __launch_bounds__(RT) void copy_blocks(const CopyDesc *tab) {
+  const CopyDesc &c = tab[blockIdx.z];
+  const int64_t tot = c.rows * c.cols;
+  for (int64_t k = (int64_t)blockIdx.x * RT + threadIdx.x; k < tot; k += (int64_t)gridDim.x * RT) {
+    const int64_t j = k / c.rows, i = k % c.rows;
+    c.dst[j * c.ldd + i] = c.src[j * c.lds + i];
+  }
+}
+
+dim3 grid3(int64_t x, int64_t y, int64_t z) { return dim3((unsigned)(x < 1 ? 1 : x), (unsigned)(y < 1 ? 1 : y), (unsigned)z); }
 
 }  // namespace
 
-// Scratch layout: kFroBlocks doubles (column-block sums of squares of A),
-// then the residual partial sums (chunks x m x nrhs compensated pairs).
 size_t refine_partial_bytes(int64_t m, int64_t n, int64_t nrhs) {
   const int64_t nch = (n + RCHUNK - 1) / RCHUNK;
   return (size_t)kFroBlocks * sizeof(double) + (size_t)(nch * m * nrhs) * sizeof(dd);
 }
 
-hipError_t refine_start(RefineState *st, hipStream_t s) {
-  hipLaunchKernelGGL(start, dim3(1), dim3(64), 0, s, st);
+// Launch helpers: `tab` null means the single problem `one`; otherwise
+// `count` problems whose largest sizes are mmax, nmax.
+hipError_t refine_start(const RefProb *tab, const RefProb &one, int count, hipStream_t s) {
+  hipLaunchKernelGGL(start, dim3(1), dim3(RT), 0, s, tab, one, count);
   return hipGetLastError();
 }
 
-hipError_t refine_fro(const double *A, int64_t lda, int64_t m, int64_t n, void *partial, hipStream_t s) {
-  double *fro = static_cast<double *>(partial);
-  hipLaunchKernelGGL(fro_partial, dim3(kFroBlocks), dim3(RT), 0, s, A, lda, m, n, fro);
+hipError_t refine_fro(const RefProb *tab, const RefProb &one, int count, hipStream_t s) {
+  hipLaunchKernelGGL(fro_partial, grid3(kFroBlocks, 1, count), dim3(RT), 0, s, tab, one);
   return hipGetLastError();
 }
 
-hipError_t refine_residual(const double *A, int64_t lda, int64_t m, int64_t n, const double *X, int64_t ldx,
-                           const double *B, int64_t ldb, int64_t nrhs, double *R, int64_t ldr, double *S,
-                           int64_t lds, void *partial, const RefineState *st, hipStream_t s) {
-  const int nch = (int)((n + RCHUNK - 1) / RCHUNK);
-  dd *p = reinterpret_cast<dd *>(static_cast<char *>(partial) + (size_t)kFroBlocks * sizeof(double));
-  const unsigned rb = (unsigned)((m + RT - 1) / RT);
-  hipLaunchKernelGGL(resid_partial, dim3(rb, nch, (unsigned)nrhs), dim3(RT), 0, s, A, lda, m, n, X, ldx, p, st);
-  hipLaunchKernelGGL(resid_reduce, dim3(rb, (unsigned)nrhs), dim3(RT), 0, s, m, nch, p, B, ldb, R, ldr, st);
-  if (S)
-    hipLaunchKernelGGL(atr, dim3((unsigned)((n + RT / 64 - 1) / (RT / 64)), (unsigned)nrhs), dim3(RT), 0, s, A,
-                       lda, m, n, R, ldr, S, lds, st);
+hipError_t refine_residual(const RefProb *tab, const RefProb &one, int count, int64_t mmax, int64_t nmax,
+                           hipStream_t s) {
+  const int64_t nch = (nmax + RCHUNK - 1) / RCHUNK;
+  const int64_t rb = (mmax + RT - 1) / RT;
+  hipLaunchKernelGGL(resid_partial, grid3(rb, nch, count), dim3(RT), 0, s, tab, one);
+  hipLaunchKernelGGL(resid_reduce, grid3(rb, 1, count), dim3(RT), 0, s, tab, one);
+  hipLaunchKernelGGL(atr, grid3((nmax + RT / 64 - 1) / (RT / 64), 1, count), dim3(RT), 0, s, tab, one);
   return hipGetLastError();
 }
 
-hipError_t refine_check(int64_t m, int64_t n, int64_t nrhs, const double *R, int64_t ldr, const double *S,
-                        int64_t lds, const double *X, int64_t ldx, const double *B, int64_t ldb,
-                        const void *partial, double tol, int it, RefineState *st, hipStream_t s) {
-  const double *fro = static_cast<const double *>(partial);
-  hipLaunchKernelGGL(check, dim3(1), dim3(RT), 0, s, m, n, nrhs, R, ldr, S, lds, X, ldx, B, ldb, fro,
-                     kFroBlocks, tol, S ? 0 : 1, it, st);
+hipError_t refine_check(const RefProb *tab, const RefProb &one, int count, double tol, int it, hipStream_t s) {
+  hipLaunchKernelGGL(check, grid3(1, 1, count), dim3(RT), 0, s, tab, one, tol, it);
   return hipGetLastError();
 }
 
-hipError_t refine_update(int64_t n, int64_t nrhs, double *X, int64_t ldx, const double *D, int64_t ldd,
-                         const RefineState *st, hipStream_t s) {
-  const int64_t tot = n * nrhs;
-  hipLaunchKernelGGL(update, dim3((unsigned)((tot + RT - 1) / RT)), dim3(RT), 0, s, n, nrhs, X, ldx, D, ldd, st);
+hipError_t refine_update(const RefProb *tab, const RefProb &one, int count, int64_t nmax, int64_t nrhs,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(update, grid3((nmax * nrhs + RT - 1) / RT, 1, count), dim3(RT), 0, s, tab, one);
   return hipGetLastError();
 }
 
-hipError_t refine_finish(const RefineState *st, int32_t *info, int32_t noconv, hipStream_t s) {
-  hipLaunchKernelGGL(finish, dim3(1), dim3(64), 0, s, st, info, noconv);
+hipError_t refine_finish(const RefProb *tab, const RefProb &one, int count, int32_t noconv, hipStream_t s) {
+  hipLaunchKernelGGL(finish, dim3(1), dim3(RT), 0, s, tab, one, count, noconv);
+  return hipGetLastError();
+}
+
+hipError_t copy_batch(const CopyDesc *tab, int count, int64_t max_elems, hipStream_t s) {
+  int64_t blocks = (max_elems + RT - 1) / RT;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(copy_blocks, grid3(blocks, 1, count), dim3(RT), 0, s, tab);
   return hipGetLastError();
 }
 

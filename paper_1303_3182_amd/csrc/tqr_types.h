@@ -28,7 +28,8 @@ struct Task {
   int32_t kind;
   int32_t i, piv, k, j;
   int32_t stripe;
-  int32_t pad0, pad1;
+  int32_t prob;   // problem index (batched launches), else 0
+  int32_t pad1;
 };
 
 // Executor control block at the start of the executor-state region.
@@ -39,6 +40,22 @@ struct ExecCtl {
   int32_t abort;   // set by the watchdog
   int32_t error;   // 0 or TQR_INFO_TIMEOUT
   int32_t pad[11];
+};
+
+// One least-squares / factorization problem as the tile kernels see it.
+struct Problem {
+  double *A;        // the matrix (factored in place)
+  int64_t lda, m, n;
+  double *B;        // right-hand sides (apply / solve), may be null
+  int64_t ldb, nrhs;
+  double *Tf;       // T factors: ((i*q + k)*2 + which) * ib * nb doubles
+  int32_t p, q;     // tile rows / columns
+  int32_t sw;       // stripe width of updates of A's columns (columns per task)
+  int32_t sw_b;     // stripe width of tasks on B's columns
+  int32_t dma_ok;   // A is 16-byte aligned with even lda: tiles may be DMA'd to LDS
+  int32_t update_dtype;  // arithmetic of the updates of A's columns: 0 FP64, 1 FP32, 2 BF16
+  int32_t *singular;     // receives min(1-based j) with R(j,j) == 0 (initially 0x7fffffff)
+  const int32_t *skip;   // optional: this problem's tasks do nothing while *skip != 0
 };
 
 // Everything the device needs for one launch.
@@ -54,17 +71,12 @@ struct ExecArgs {
   ExecCtl *ctl;
   int32_t *queue;   // ntasks slots
   int32_t *indeg;   // working dependency counts
-  // problem
-  double *A;
-  int64_t lda, m, n;
-  double *B;        // right-hand sides (apply / solve), may be null
-  int64_t ldb, nrhs;
-  double *Tf;       // T factors: ((i*q + k)*2 + which) * ib * nb doubles
-  int32_t p, q, nb, ib;
-  int32_t sw;       // stripe width of updates of A's columns (columns per task)
-  int32_t sw_b;     // stripe width of tasks on B's columns
-  int32_t dma_ok;   // A is 16-byte aligned with even lda: tiles may be DMA'd to LDS
-  int32_t update_dtype;  // arithmetic of the updates of A's columns: 0 FP64, 1 FP32, 2 BF16
+  // the problem (single launches), or a table indexed by Task::prob (batched)
+  Problem prob;
+  const Problem *probs;
+  int32_t nprob;    // entries of probs
+  int32_t pad_;
+  int32_t nb, ib;
   int64_t spin_limit;  // watchdog, in wall-clock ticks
   int64_t *trace;      // optional: per task {start, end, workgroup, xcc}
   int64_t trace_cap;   // tasks that fit in `trace`

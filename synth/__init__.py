@@ -64,12 +64,13 @@ def ragged_batch_shapes(count, seed, m_range=(256, 8192), n_range=(32, 512)):
     return shapes
 
 
-def ragged_batch(count, seed, **kw):
-    """List of (A, b) with i.i.d. N(0,1) entries for the ragged batch."""
-    out = []
-    for idx, (m, n) in enumerate(ragged_batch_shapes(count, seed, **kw)):
+def ragged_batch(shapes, seed, nrhs=1):
+    """Matrices and right-hand sides of a ragged batch, i.i.d. N(0,1):
+    lists As (m x n) and Bs (m x nrhs), column-major, one generator stream
+    per problem."""
+    As, Bs = [], []
+    for idx, (m, n) in enumerate(shapes):
         rng = np.random.default_rng([seed, idx])
-        A = np.asfortranarray(rng.standard_normal((m, n)))
-        b = rng.standard_normal(m)
-        out.append((A, b))
-    return out
+        As.append(np.asfortranarray(rng.standard_normal((m, n))))
+        Bs.append(np.asfortranarray(rng.standard_normal((m, nrhs))))
+    return As, Bs

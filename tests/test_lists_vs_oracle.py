@@ -104,3 +104,24 @@ def test_fused_least_squares_graph():
             assert kinds.count(3) == fk.count(3) + fk.count(0)
             assert kinds.count(5) == fk.count(5) + fk.count(2)
         assert ls[0][7] == 0
+
+
+def test_batched_host_checks():
+    """Batch sizing and argument checks are host-only."""
+    import ctypes
+    L = T.lib()
+    i64 = ctypes.c_int64
+    ms = (i64 * 3)(300, 500, 1000)
+    ns = (i64 * 3)(100, 33, 400)
+    o = T.default_opts(nb=64, ib=16)
+    w1 = L.tqr_lstsq_batched_work_size(3, ms, ns, 1, T._binding._opts_ptr(o))
+    w2 = L.tqr_lstsq_batched_work_size(3, ms, ns, 4, T._binding._opts_ptr(o))
+    wall = L.tqr_lstsq_batched_work_size(3, ms, ns, 1, T._binding._opts_ptr(T.default_opts(nb=0)))
+    assert 0 < w1 < w2 and wall >= w1
+    # at least the copies of A and B and the T factors of every problem
+    assert w1 >= 8 * sum(m * n + m for m, n in [(300, 100), (500, 33), (1000, 400)])
+    bad = (i64 * 3)(100, 600, 400)   # n > m for the second problem
+    assert L.tqr_lstsq_batched_work_size(3, ms, bad, 1, T._binding._opts_ptr(o)) == 0
+    nul = ctypes.POINTER(ctypes.c_void_p)()
+    assert L.tqr_lstsq_batched(0, ms, ns, 1, nul, None, nul, None, nul, None, None, 0, None, None, None) == -1
+    assert L.tqr_lstsq_batched(3, ms, bad, 1, nul, None, nul, None, nul, None, None, 0, None, None, None) == -2
