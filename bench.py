@@ -1,17 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark of the tiled QR path on one MI355X.
 
-Workload: FP64 least squares on a tall-skinny matrix, m = 16384, n = 2048,
-tile nb = 256 (64 x 8 tiles), entries i.i.d. N(0,1) (seeded, synthetic),
-GrASAP elimination tree, TT kernels.  One step is the whole hot path on one
-batch: tqr_lstsq, i.e. copy A and b into the workspace, then one persistent
-executor launch that factors A = QR, applies Q^T to b as the factorization
-proceeds, and back-substitutes R x = (Q^T b)(1:n) (elimination list and
-task graph are cached after the first call).
+Default workload (--workload tall): FP64 least squares on a tall-skinny
+matrix, m = 16384, n = 2048, tile nb = 256 (64 x 8 tiles), entries i.i.d.
+N(0,1) (seeded, synthetic), GrASAP elimination tree, TT kernels.  One step
+is the whole hot path on one batch: tqr_lstsq, i.e. copy A and b into the
+workspace, then one persistent executor launch that factors A = QR, applies
+Q^T to b as the factorization proceeds, and back-substitutes
+R x = (Q^T b)(1:n) (elimination list and task graph are cached after the
+first call).  The same solve is then timed with FP32 and BF16 trailing
+updates plus FP64 refinement to the FP64 backward error.
 
-value = 2 n^2 (m - n/3) / (seconds per step), in TFLOP/s: only the QR flops
-are counted although the step also applies Q^T and solves.  Inputs are
-resident in HBM when the timed region starts.
+Other workloads (each prints its own JSON line):
+  --workload square   8192 x 8192 systems A = U diag(sigma) V^T with Haar U,
+                      V, log-spaced sigma, kappa in {1e2, 1e5, 1e8},
+                      b = A x + 1e-6 N(0,1); FP64, FP32 and BF16 updates.
+  --workload batched  512 ragged least-squares problems, m log-uniform in
+                      [256, 8192], n log-uniform in [32, 512], n <= m/2,
+                      N(0,1); FP32 updates + FP64 refinement, nb/ib from the
+                      autotuner, tree per problem by critical path; one
+                      executor launch per solve.
+
+value = sum of 2 n^2 (m - n/3) over the problems / (seconds per step), in
+TFLOP/s: only the QR flops are counted although the step also applies Q^T
+and solves (and refines).  Inputs are resident in HBM when the timed region
+starts.
 
 The JSON line also carries the roofline of the dominant kernel (the
 executor launch, timed by HIP events that the library records around each
@@ -29,6 +42,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "QR TFLOP/s (2n²(m−n/3)) plain FP64 vs mixed+refined at equal FP64 error"
 PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix peak
+EPS = 2.0 ** -52
 
 
 def log(msg):
@@ -40,25 +54,219 @@ def qr_flops(m, n):
     return 2.0 * n * n * (m - n / 3.0)
 
 
-def cpu_baseline(A0, ncols):
-    """The FP64 oracle (unblocked Householder, numpy) on the first `ncols`
-    columns of the workload matrix: a bounded sample, rate in TFLOP/s of the
-    same flop formula."""
-    from oracle import householder as H
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+        return max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
     except Exception:  # pragma: no cover
-        cores = 1
-    S = A0[:, :ncols].copy(order="F")
+        return 1
+
+
+def oracle_qr_rate(S, what):
+    """The FP64 oracle (unblocked Householder, numpy) on the sample S, as a
+    rate in TFLOP/s of the same flop formula."""
+    from oracle import householder as H
     t0 = time.perf_counter()
     H.qr(S)
     dt = time.perf_counter() - t0
-    m = S.shape[0]
-    return {"value": qr_flops(m, ncols) / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores),
-            "kind": "oracle", "seconds": dt,
-            "sample": "unblocked FP64 Householder QR of the first %d columns of the %dx%d workload "
-                      "matrix (%d x %d)" % (ncols, m, A0.shape[1], m, ncols)}
+    m, n = S.shape
+    return {"value": qr_flops(m, n) / dt / 1e12, "unit": "TFLOP/s", "cores": int(blas_threads()),
+            "kind": "oracle", "seconds": dt, "sample": what}
+
+
+def timed(fn, steps, warmup, torch, T):
+    """Runs fn warmup times, then `steps` times inside the timed region;
+    returns (ms per step by the host clock, mean executor launch ms, launches
+    per step)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    T.debug_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms, launches = T.debug_timing_read()
+    T.debug_timing(False)
+    return (t1 - t0) / steps * 1e3, kern_ms / max(launches, 1), launches / steps
+
+
+def roofline(flops, kernel_ms, kernel):
+    achieved = flops / (kernel_ms / 1e3) / 1e12
+    return {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_MFMA, "traffic": None, "kernel": kernel}
+
+
+def base_line(args, value, ms, dtype, config):
+    return {"metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+# --------------------------------------------------------------- tall-skinny
+def run_tall(args, np, torch, T, synth):
+    m, n, nb = args.m, args.n, args.nb
+    log("workload %dx%d nb=%d tree=%s kernels=%s" % (m, n, nb, args.tree, args.kernels))
+    A0 = synth.gaussian(m, n, 1)
+    b0 = synth.gaussian_rhs(m, 1, 1)
+    dev = torch.device("cuda:0")
+    opts = T.default_opts(nb=nb, ib=args.ib, tree=args.tree, kernels=args.kernels, stripes=args.stripes)
+    A = T.colmajor(A0, dev)
+    b = T.colmajor(b0, dev)
+    X = torch.empty((1, n), dtype=torch.float64, device=dev).t()
+    work = T.lstsq_workspace(m, n, 1, opts, dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    ms, kms, _ = timed(lambda: T.lstsq(A, b, opts, X=X, work=work, info=info), args.steps, args.warmup, torch, T)
+    log("timed %d steps: %.3f ms/step, executor launch %.3f ms" % (args.steps, ms, kms))
+    if int(info.item()) != 0:
+        raise SystemExit("executor reported info=%d" % int(info.item()))
+
+    # accuracy: Stewart's one-sided backward error bound ||A^T r|| / (||A||_F ||r||)
+    # in extended precision
+    Al = A0.astype(np.longdouble)
+
+    def backward_error(x):
+        r = b0[:, 0].astype(np.longdouble) - Al @ x.astype(np.longdouble)
+        return float(np.linalg.norm((Al.T @ r).astype(np.float64)) /
+                     (np.linalg.norm(A0) * np.linalg.norm(r.astype(np.float64))))
+
+    be = backward_error(X[:, 0].cpu().numpy())
+    mixed = {}
+    for dt in args.mixed:
+        om = T.default_opts(nb=nb, ib=args.ib, tree=args.tree, kernels=args.kernels, stripes=args.stripes,
+                            update_dtype=dt, max_refine=20)
+        wm = T.lstsq_workspace(m, n, 1, om, dev)
+        mms, mkms, nl = timed(lambda: T.lstsq(A, b, om, X=X, work=wm, info=info), args.steps, args.warmup,
+                              torch, T)
+        rep = T.refine_report(wm)
+        inf = int(info.item())
+        mbe = backward_error(X[:, 0].cpu().numpy())
+        log("mixed %s: %.3f ms/step, %d refinement steps, backward error %.2e (info %d)" %
+            (dt, mms, rep["iterations"], mbe, inf))
+        mixed[dt] = {"ms_per_step": mms, "value": qr_flops(m, n) / (mms / 1e3) / 1e12, "unit": "TFLOP/s",
+                     "speedup_vs_fp64": ms / mms, "refine_steps": rep["iterations"], "converged": rep["done"],
+                     "info": inf, "ls_backward_error": mbe, "equal_fp64_error": bool(mbe <= 50 * EPS)}
+    out = base_line(args, qr_flops(m, n) / (ms / 1e3) / 1e12, ms, "f64",
+                    {"workload": "FP64 tiled-QR least squares, tall-skinny %dx%d, nb=%d (%dx%d tiles), "
+                                 "N(0,1) entries, seed 1" % (m, n, nb, -(-m // nb), -(-n // nb)),
+                     "m": m, "n": n, "nb": nb, "ib": args.ib, "tree": args.tree,
+                     "kernels": args.kernels, "precision": "plain FP64"})
+    out["executor_ms"] = kms
+    out["ls_backward_error"] = be
+    out["mixed_precision"] = mixed
+    out["roofline"] = roofline(qr_flops(m, n), kms,
+                               "exec_persistent (least-squares task graph: factor, Q^T b, R x = c)")
+    if not args.no_cpu_baseline:
+        c = args.cpu_sample_cols
+        log("cpu baseline: oracle on a %d-column sample" % c)
+        out["cpu_baseline"] = oracle_qr_rate(
+            A0[:, :c].copy(order="F"), "unblocked FP64 Householder QR of the first %d columns of the %dx%d "
+                                       "workload matrix (%d x %d)" % (c, m, n, m, c))
+    return out
+
+
+# -------------------------------------------------------------------- square
+def run_square(args, np, torch, T, synth):
+    n, nb = args.square_n, args.nb
+    dev = torch.device("cuda:0")
+    X = torch.empty((1, n), dtype=torch.float64, device=dev).t()
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    per_kappa = {}
+    fp64_ms = fp64_kms = None
+    for kappa in args.kappas:
+        t0 = time.perf_counter()
+        A0, x0, b0 = synth.conditioned(n, kappa, 7)
+        log("kappa %g: inputs in %.1f s" % (kappa, time.perf_counter() - t0))
+        A = T.colmajor(A0, dev)
+        b = T.colmajor(b0[:, None], dev)
+        res = {}
+        for dt in ["f64"] + list(args.mixed):
+            o = T.default_opts(nb=nb, ib=args.ib, tree=args.tree, update_dtype=dt, max_refine=20)
+            w = T.lstsq_workspace(n, n, 1, o, dev)
+            ms, kms, nl = timed(lambda: T.lstsq(A, b, o, X=X, work=w, info=info), args.steps, args.warmup, torch, T)
+            x = X[:, 0].cpu().numpy()
+            r = b0 - A0 @ x
+            be = float(np.linalg.norm(r) / (np.linalg.norm(A0) * np.linalg.norm(x) + np.linalg.norm(b0)))
+            rep = T.refine_report(w)
+            res[dt] = {"ms_per_step": ms, "value": qr_flops(n, n) / (ms / 1e3) / 1e12,
+                       "refine_steps": rep["iterations"], "converged": rep["done"], "info": int(info.item()),
+                       "backward_error": be, "equal_fp64_error": bool(be <= 50 * EPS)}
+            if dt == "f64" and fp64_ms is None:
+                fp64_ms, fp64_kms = ms, kms
+            log("kappa %g %s: %.2f ms, be %.2e, refine %d, info %d" % (kappa, dt, ms, be, rep["iterations"],
+                                                                     int(info.item())))
+        for dt in args.mixed:
+            res[dt]["speedup_vs_fp64"] = res["f64"]["ms_per_step"] / res[dt]["ms_per_step"]
+        per_kappa["%g" % kappa] = res
+        del A, b
+    out = base_line(args, qr_flops(n, n) / (fp64_ms / 1e3) / 1e12, fp64_ms, "f64",
+                    {"workload": "FP64 tiled-QR solve of square %dx%d systems with prescribed condition number "
+                                 "(Haar U, V; log-spaced sigma), nb=%d, %s tree" % (n, n, nb, args.tree),
+                     "n": n, "nb": nb, "ib": args.ib, "tree": args.tree, "kappas": args.kappas})
+    out["executor_ms"] = fp64_kms
+    out["per_kappa"] = per_kappa
+    out["roofline"] = roofline(qr_flops(n, n), fp64_kms, "exec_persistent (least-squares task graph)")
+    if not args.no_cpu_baseline:
+        A0, _, _ = synth.conditioned(n, args.kappas[0], 7)
+        c = 64
+        out["cpu_baseline"] = oracle_qr_rate(A0[:, :c].copy(order="F"),
+                                             "unblocked FP64 Householder QR of the first %d columns of the "
+                                             "%dx%d kappa=%g matrix" % (c, n, n, args.kappas[0]))
+    return out
+
+
+# ------------------------------------------------------------------- batched
+def run_batched(args, np, torch, T, synth):
+    from oracle import householder as H
+    dev = torch.device("cuda:0")
+    shapes = synth.ragged_batch_shapes(args.batch, 0)
+    As, Bs = synth.ragged_batch(shapes, 0, 1)
+    flops = sum(qr_flops(m, n) for m, n in shapes)
+    log("batch of %d problems, %.3g QR flops" % (len(shapes), flops))
+    dA = [T.colmajor(a, dev) for a in As]
+    dB = [T.colmajor(b, dev) for b in Bs]
+    Xs = [torch.empty((1, n), dtype=torch.float64, device=dev).t() for _, n in shapes]
+    info = torch.zeros(len(shapes), dtype=torch.int32, device=dev)
+    results = {}
+    for dt in ["f64"] + list(args.mixed):
+        o = T.default_opts(tree="auto", update_dtype=dt, max_refine=20)
+        tune_ms = T.autotune_batched(dA, dB, o, Xs=Xs)
+        work = T.lstsq_batched_workspace(shapes, 1, o, dev)
+        ms, kms, nl = timed(lambda: T.lstsq_batched(dA, dB, o, Xs=Xs, work=work, info=info), args.steps,
+                            args.warmup, torch, T)
+        bad = int((info != 0).sum().item())
+        sample = list(range(0, len(shapes), max(1, len(shapes) // 16)))
+        bes = [H.ls_backward_error(As[x], Bs[x][:, 0], Xs[x][:, 0].cpu().numpy()) for x in sample]
+        reps = T.refine_reports(work, len(shapes)) if dt != "f64" else []
+        results[dt] = {"ms_per_step": ms, "value": flops / (ms / 1e3) / 1e12, "executor_ms": kms,
+                       "launches_per_step": nl, "nb": o.nb, "ib": o.ib, "autotune_best_ms": tune_ms,
+                       "problems_with_info": bad, "max_backward_error_sample": max(bes),
+                       "sample_problems": len(sample), "equal_fp64_error": bool(max(bes) <= 50 * EPS)}
+        if reps:
+            results[dt]["max_refine_steps"] = max(r["iterations"] for r in reps)
+            results[dt]["converged"] = sum(r["done"] for r in reps)
+        log("batched %s: nb=%d ib=%d %.2f ms/step (%.2f TFLOP/s), max be %.2e" %
+            (dt, o.nb, o.ib, ms, flops / (ms / 1e3) / 1e12, max(bes)))
+    for dt in args.mixed:
+        results[dt]["speedup_vs_fp64"] = results["f64"]["ms_per_step"] / results[dt]["ms_per_step"]
+    lead = args.mixed[0] if args.mixed else "f64"
+    r0 = results[lead]
+    out = base_line(args, r0["value"], r0["ms_per_step"], lead,
+                    {"workload": "batched ragged least squares: %d problems, m log-uniform [256, 8192], "
+                                 "n log-uniform [32, 512], n <= m/2, N(0,1), seed 0; %s updates + FP64 "
+                                 "refinement; autotuned nb/ib, tree per problem" % (len(shapes), lead),
+                     "problems": len(shapes), "qr_flops": flops})
+    out["per_dtype"] = results
+    out["roofline"] = roofline(flops, r0["executor_ms"] * r0["launches_per_step"],
+                               "exec_persistent (batched least-squares task graph; all executor launches "
+                               "of one step)")
+    if not args.no_cpu_baseline:
+        x = int(np.argmax([m * n for m, n in shapes]))
+        out["cpu_baseline"] = oracle_qr_rate(As[x].copy(order="F"),
+                                             "unblocked FP64 Householder QR of the batch's largest problem "
+                                             "(%d x %d)" % shapes[x])
+    return out
 
 
 def main():
@@ -66,8 +274,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["tall", "square", "batched"], default="tall")
     ap.add_argument("--m", type=int, default=16384)
     ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--square-n", type=int, default=8192)
+    ap.add_argument("--kappas", type=float, nargs="*", default=[1e2, 1e5, 1e8])
+    ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--nb", type=int, default=256)
     ap.add_argument("--ib", type=int, default=32)
     ap.add_argument("--tree", default="grasap")
@@ -89,105 +301,9 @@ def main():
     import paper_1303_3182_amd as T
     import synth
 
-    m, n, nb = args.m, args.n, args.nb
-    log("workload %dx%d nb=%d tree=%s kernels=%s" % (m, n, nb, args.tree, args.kernels))
-    A0 = synth.gaussian(m, n, 1)
-    b0 = synth.gaussian_rhs(m, 1, 1)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    opts = T.default_opts(nb=nb, ib=args.ib, tree=args.tree, kernels=args.kernels, stripes=args.stripes)
-    A = T.colmajor(A0, dev)
-    b = T.colmajor(b0, dev)
-    X = torch.empty((1, n), dtype=torch.float64, device=dev).t()
-    work = T.lstsq_workspace(m, n, 1, opts, dev)
-    info = torch.zeros(1, dtype=torch.int32, device=dev)
-
-    def step():
-        T.lstsq(A, b, opts, X=X, work=work, info=info)
-
-    for w in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("warmup done (%d steps)" % args.warmup)
-    T.debug_timing(True)
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kern_ms, launches = T.debug_timing_read()
-    T.debug_timing(False)
-    ms = (t1 - t0) / args.steps * 1e3
-    factor_ms = kern_ms / launches
-    log("timed %d steps: %.3f ms/step, executor launch %.3f ms (%d launches)" % (args.steps, ms, factor_ms, launches))
-    if int(info.item()) != 0:
-        raise SystemExit("executor reported info=%d" % int(info.item()))
-
-    # accuracy of the last step's solution: Stewart's one-sided backward
-    # error bound ||A^T r|| / (||A||_F ||r||) in extended precision
-    Al = A0.astype(np.longdouble)
-
-    def backward_error(x):
-        r = b0[:, 0].astype(np.longdouble) - Al @ x.astype(np.longdouble)
-        return float(np.linalg.norm((Al.T @ r).astype(np.float64)) /
-                     (np.linalg.norm(A0) * np.linalg.norm(r.astype(np.float64))))
-
-    be = backward_error(X[:, 0].cpu().numpy())
-
-    # the same least-squares solve with low-precision trailing updates and
-    # FP64 refinement to the FP64 backward error
-    mixed = {}
-    for dt in args.mixed:
-        om = T.default_opts(nb=nb, ib=args.ib, tree=args.tree, kernels=args.kernels, stripes=args.stripes,
-                            update_dtype=dt, max_refine=20)
-        wm = T.lstsq_workspace(m, n, 1, om, dev)
-        for w in range(args.warmup):
-            T.lstsq(A, b, om, X=X, work=wm, info=info)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s in range(args.steps):
-            T.lstsq(A, b, om, X=X, work=wm, info=info)
-        torch.cuda.synchronize()
-        mms = (time.perf_counter() - t0) / args.steps * 1e3
-        rep = T.refine_report(wm)
-        inf = int(info.item())
-        mbe = backward_error(X[:, 0].cpu().numpy())
-        log("mixed %s: %.3f ms/step, %d refinement steps, backward error %.2e (info %d)" %
-            (dt, mms, rep["iterations"], mbe, inf))
-        mixed[dt] = {"ms_per_step": mms, "value": qr_flops(m, n) / (mms / 1e3) / 1e12, "unit": "TFLOP/s",
-                     "speedup_vs_fp64": ms / mms, "refine_steps": rep["iterations"], "converged": rep["done"],
-                     "info": inf, "ls_backward_error": mbe, "equal_fp64_error": bool(mbe <= 50 * 2.0 ** -52)}
-
-    flops = qr_flops(m, n)
-    achieved = flops / (factor_ms / 1e3) / 1e12
-    out = {
-        "metric": METRIC,
-        "value": flops / (ms / 1e3) / 1e12,
-        "unit": "TFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "FP64 tiled-QR least squares, tall-skinny %dx%d, nb=%d (%dx%d tiles), "
-                               "N(0,1) entries, seed 1" % (m, n, nb, -(-m // nb), -(-n // nb)),
-                   "m": m, "n": n, "nb": nb, "ib": args.ib, "tree": args.tree,
-                   "kernels": args.kernels, "precision": "plain FP64"},
-        "executor_ms": factor_ms,
-        "ls_backward_error": be,
-        "mixed_precision": mixed,
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
-                     "kernel": "exec_persistent (least-squares task graph: factor, Q^T b, R x = c)"},
-    }
-    if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on a %d-column sample" % args.cpu_sample_cols)
-        out["cpu_baseline"] = cpu_baseline(A0, args.cpu_sample_cols)
-    print(json.dumps(out))
+    torch.cuda.set_device(0)
+    run = {"tall": run_tall, "square": run_square, "batched": run_batched}[args.workload]
+    print(json.dumps(run(args, np, torch, T, synth)))
 
 
 if __name__ == "__main__":

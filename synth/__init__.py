@@ -9,6 +9,7 @@ The thesis's experiments do not state their matrix entry distribution; the
 workloads below follow the sizes it and the project name (i.i.d. N(0,1)
 entries, prescribed-condition square systems, ragged batches).
 """
+import functools
 import math
 
 import numpy as np
@@ -23,6 +24,11 @@ def gaussian(m, n, seed):
 def gaussian_rhs(m, nrhs, seed):
     rng = np.random.default_rng(seed + 0x5EED)
     return np.asfortranarray(rng.standard_normal((m, nrhs)))
+
+
+@functools.lru_cache(maxsize=4)
+def _haar_cached(n, seed):
+    return haar_orthogonal(n, seed)
 
 
 def haar_orthogonal(n, seed):
@@ -40,8 +46,8 @@ def conditioned(n, kappa, seed):
     """A = U diag(sigma) V^T with Haar U, V and sigma_i = kappa^(-(i-1)/(n-1)).
 
     Returns (A, x, b) with x ~ N(0,1) and b = A x + 1e-6 N(0,1)."""
-    U = haar_orthogonal(n, seed)
-    Vt = haar_orthogonal(n, seed + 1).T
+    U = _haar_cached(n, seed)
+    Vt = _haar_cached(n, seed + 1).T
     i = np.arange(n, dtype=np.float64)
     sigma = kappa ** (-i / max(n - 1, 1))
     A = np.asfortranarray((U * sigma[None, :]) @ Vt)
