@@ -213,6 +213,47 @@ int tqr_autotune_batched(int32_t count, const int64_t *m, const int64_t *n, int6
                          const int64_t *ldb, double *const *X, const int64_t *ldx, void *work,
                          size_t work_bytes, tqr_opts *o, float *best_ms, hipStream_t stream);
 
+/* ------------------------------------------------ learned tree/nb selector
+ *
+ * A 3-layer perceptron (9 inputs, two hidden layers of 64 tanh units, one
+ * output; FP32) predicts log(milliseconds) of a factorization from
+ * features of (m, n, nb, tree, batch) (tqr_mlp_features).  It is trained on
+ * the engine's own timings with the gradient and Adam kernels below and
+ * registered with tqr_set_selector; TQR_AUTO then picks, per shape, the
+ * (tree, nb) of smallest predicted time among the five trees and the built
+ * tile sizes >= 64.  Without a registered network TQR_AUTO means GrASAP at
+ * nb = 256.  (Project addition; the thesis selects trees by critical-path
+ * analysis only.)  Parameters: W1 [64 x 9], b1 [64], W2 [64 x 64], b2 [64],
+ * W3 [64], b3, contiguous FP32 in device memory. */
+int32_t tqr_mlp_params(void);
+int32_t tqr_mlp_features(void);
+/* Feature vector (host) of one candidate: log2(m)/16, log2(n)/16,
+ * log2(nb)/8, one-hot tree (FLAT, BINARY, FIBONACCI, GREEDY, GRASAP),
+ * log2(batch)/10.  Returns 0, or -4 for a tree outside the five. */
+int tqr_mlp_features_of(int64_t m, int64_t n, int32_t nb, int32_t tree, int32_t batch, float *out);
+/* Device buffers: X [batch x 9] row-major, y / target [batch]. */
+size_t tqr_mlp_work_size(int64_t batch);
+int tqr_mlp_forward(const float *params, const float *X, int64_t batch, float *y, hipStream_t stream);
+/* grad = d/dparams of mean((y - target)^2); loss (device float, may be
+ * NULL) = that mean.  work: tqr_mlp_work_size(batch) bytes. */
+int tqr_mlp_grad(const float *params, const float *X, const float *target, int64_t batch, float *grad,
+                 float *loss, void *work, size_t work_bytes, hipStream_t stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8), step >= 1; m1, m2 are
+ * the caller's moment buffers (zero before step 1). */
+int tqr_mlp_adam(float *params, const float *grad, float *m1, float *m2, int64_t step, float lr,
+                 hipStream_t stream);
+/* `epochs` full-batch Adam steps on (X, target); loss_hist (device, epochs
+ * floats, may be NULL) receives the loss before each step. */
+int tqr_mlp_fit(float *params, const float *X, const float *target, int64_t batch, int32_t epochs, float lr,
+                float *loss_hist, void *work, size_t work_bytes, hipStream_t stream);
+/* Registers (copies) a trained parameter vector from device memory; NULL
+ * clears it.  Synchronous. */
+int tqr_set_selector(const float *params);
+/* The selector's choice for an m x n problem (batch: problems solved
+ * together); host outputs.  Synchronous (runs the network on the current
+ * device).  Falls back to GrASAP, 256, 32 without a registered network. */
+int tqr_select(int64_t m, int64_t n, int32_t batch, int32_t *tree, int32_t *nb, int32_t *ib);
+
 /* ----------------------------------------------- host-only list services */
 
 /* Elimination list of `tree` (param: PlasmaTree BS / GrASAP i) for p x q

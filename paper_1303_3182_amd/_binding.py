@@ -63,6 +63,16 @@ def lib():
                                                  vp, vp]),
             "tqr_autotune_batched": (ctypes.c_int, [i32, i64p, i64p, i64, vpp, i64p, vpp, i64p, vpp, i64p, vp, sz,
                                                     op, ctypes.POINTER(ctypes.c_float), vp]),
+            "tqr_mlp_params": (i32, []),
+            "tqr_mlp_features": (i32, []),
+            "tqr_mlp_features_of": (ctypes.c_int, [i64, i64, i32, i32, i32, ctypes.POINTER(ctypes.c_float)]),
+            "tqr_mlp_work_size": (sz, [i64]),
+            "tqr_mlp_forward": (ctypes.c_int, [vp, vp, i64, vp, vp]),
+            "tqr_mlp_grad": (ctypes.c_int, [vp, vp, vp, i64, vp, vp, vp, sz, vp]),
+            "tqr_mlp_adam": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.c_float, vp]),
+            "tqr_mlp_fit": (ctypes.c_int, [vp, vp, vp, i64, i32, ctypes.c_float, vp, vp, sz, vp]),
+            "tqr_set_selector": (ctypes.c_int, [vp]),
+            "tqr_select": (ctypes.c_int, [i64, i64, i32, i32p, i32p, i32p]),
             "tqr_debug_trace": (None, [vp, i64]),
             "tqr_debug_timing": (None, [i32]),
             "tqr_debug_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), i64p]),

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <array>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -12,6 +14,7 @@
 #include <vector>
 
 #include "graph.h"
+#include "mlp.h"
 #include "refine.h"
 #include "tqr.h"
 #include "tqr_types.h"
@@ -166,7 +169,79 @@ struct Resolved {
   double refine_tol;
 };
 
-int resolve(const tqr_opts *o, Resolved *r) {
+// ------------------------------------------------------------- selector
+// Registered network (device copy) and its per-shape choices.
+struct Selector {
+  float *params = nullptr;  // device, kMlpParams floats
+  int dev = -1;
+  float *scratch = nullptr;  // features and outputs of the candidates
+  std::map<std::tuple<int64_t, int64_t, int>, std::array<int, 3>> cache;
+};
+Selector g_sel;
+
+constexpr int kSelTrees[5] = {TQR_FLAT, TQR_BINARY, TQR_FIBONACCI, TQR_GREEDY, TQR_GRASAP};
+
+int mlp_features(int64_t m, int64_t n, int nb, int tree, int batch, float *out) {
+  int slot = -1;
+  for (int t = 0; t < 5; t++)
+    if (kSelTrees[t] == tree) slot = t;
+  if (slot < 0) return -4;
+  out[0] = (float)(std::log2((double)m) / 16.0);
+  out[1] = (float)(std::log2((double)n) / 16.0);
+  out[2] = (float)(std::log2((double)nb) / 8.0);
+  for (int t = 0; t < 5; t++) out[3 + t] = (t == slot) ? 1.0f : 0.0f;
+  out[8] = (float)(std::log2((double)std::max(batch, 1)) / 10.0);
+  return 0;
+}
+
+// (tree, nb, ib) of smallest predicted time; GrASAP / 256 / 32 without a
+// registered network (or on another device than the one it was registered on).
+int select_cfg(int64_t m, int64_t n, int batch, int *tree, int *nb, int *ib) {
+  *tree = TQR_GRASAP;
+  *nb = 256;
+  *ib = 32;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int dev = -1;
+  if (!g_sel.params || hipGetDevice(&dev) != hipSuccess || dev != g_sel.dev) return TQR_OK;
+  auto key = std::make_tuple(m, n, batch);
+  auto it = g_sel.cache.find(key);
+  if (it != g_sel.cache.end()) {
+    *tree = it->second[0];
+    *nb = it->second[1];
+    *ib = it->second[2];
+    return TQR_OK;
+  }
+  int nbs[16], ibs[16];
+  const int nc = std::min(config_list(nbs, ibs, 16), 16);
+  std::vector<std::array<int, 3>> cand;
+  for (int c = 0; c < nc; c++) {
+    if (nbs[c] < 64) continue;
+    bool better_ib = false;  // one ib per nb: the largest built
+    for (int d = 0; d < nc; d++)
+      if (nbs[d] == nbs[c] && ibs[d] > ibs[c]) better_ib = true;
+    if (better_ib) continue;
+    for (int t : kSelTrees) cand.push_back({t, nbs[c], ibs[c]});
+  }
+  const int K = (int)cand.size();
+  std::vector<float> feat((size_t)K * kMlpFeatures), pred((size_t)K);
+  for (int k = 0; k < K; k++) mlp_features(m, n, cand[k][1], cand[k][0], batch, &feat[(size_t)k * kMlpFeatures]);
+  float *dX = g_sel.scratch, *dY = g_sel.scratch + 1024 * kMlpFeatures;
+  if (K > 1024) return TQR_E_INTERNAL;
+  if (hipMemcpy(dX, feat.data(), feat.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      mlp_forward(g_sel.params, dX, K, dY, nullptr) != hipSuccess ||
+      hipMemcpy(pred.data(), dY, pred.size() * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+    return TQR_E_HIP;
+  int best = 0;
+  for (int k = 1; k < K; k++)
+    if (pred[k] < pred[best]) best = k;
+  *tree = cand[best][0];
+  *nb = cand[best][1];
+  *ib = cand[best][2];
+  g_sel.cache[key] = cand[best];
+  return TQR_OK;
+}
+
+int resolve(const tqr_opts *o, Resolved *r, int64_t m = 0, int64_t n = 0) {
   tqr_opts d;
   tqr_default_opts(&d);
   const tqr_opts &x = o ? *o : d;
@@ -178,8 +253,16 @@ int resolve(const tqr_opts *o, Resolved *r) {
   r->priority = x.priority;
   r->exec = x.exec;
   if (r->tree == TQR_AUTO) {
-    r->tree = TQR_GRASAP;
-    r->param = 1;
+    // the learned selector picks tree and tile size for this shape
+    int t = TQR_GRASAP, nb = 256, ib = 32;
+    if (m > 0 && n > 0) {
+      const int rc = select_cfg(m, n, 1, &t, &nb, &ib);
+      if (rc) return rc;
+    }
+    r->tree = t;
+    r->param = (t == TQR_GRASAP) ? 1 : 0;
+    r->nb = nb;
+    r->ib = ib;
   }
   if (!config_supported(r->nb, r->ib)) return TQR_E_UNSUPPORTED;
   if (r->tree < TQR_FLAT || r->tree > TQR_ASAP) return TQR_E_UNSUPPORTED;
@@ -628,7 +711,7 @@ void tqr_default_opts(tqr_opts *o) {
 size_t tqr_workspace_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o) {
   if (m < 1 || n < 1 || n > m || nrhs < 0) return 0;
   Resolved r;
-  if (resolve(o, &r)) return 0;
+  if (resolve(o, &r, m, n)) return 0;
   const int64_t p = cdiv(m, r.nb), q = cdiv(n, r.nb);
   int64_t nt = plan_tasks(PK_FACTOR, m, n, 0, r);
   if (nrhs > 0) {
@@ -646,7 +729,7 @@ int tqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, void *T, size_t 
   if (lda < m) return -4;
   if (!T) return -5;
   Resolved r;
-  int rc = resolve(o, &r);
+  int rc = resolve(o, &r, m, n);
   if (rc) return rc;
   return run_plan(PK_FACTOR, m, n, A, lda, nullptr, 0, 0, T, t_bytes, r, info, stream);
 }
@@ -674,7 +757,7 @@ int tqr_apply_qt(int64_t m, int64_t n, const double *A, int64_t lda, void *T, si
   if (ldb < m) return -9;
   if (nrhs == 0) return TQR_OK;
   Resolved r;
-  int rc = resolve(o, &r);
+  int rc = resolve(o, &r, m, n);
   if (rc) return rc;
   return run_plan(PK_APPLY, m, n, const_cast<double *>(A), lda, B, ldb, nrhs, T, t_bytes, r, info,
                   stream);
@@ -693,7 +776,7 @@ int tqr_solve_r(int64_t m, int64_t n, const double *A, int64_t lda, void *T, siz
   if (ldb < m) return -9;
   if (nrhs == 0) return TQR_OK;
   Resolved r;
-  int rc = resolve(o, &r);
+  int rc = resolve(o, &r, m, n);
   if (rc) return rc;
   return run_plan(PK_SOLVE, m, n, const_cast<double *>(A), lda, B, ldb, nrhs, T, t_bytes, r, info,
                   stream);
@@ -702,7 +785,7 @@ int tqr_solve_r(int64_t m, int64_t n, const double *A, int64_t lda, void *T, siz
 size_t tqr_lstsq_work_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o) {
   if (m < 1 || n < 1 || n > m || nrhs < 1) return 0;
   Resolved r;
-  if (resolve(o, &r)) return 0;
+  if (resolve(o, &r, m, n)) return 0;
   return ls_layout(m, n, nrhs, r).total;
 }
 
@@ -720,7 +803,7 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
   if (ldx < n) return -9;
   if (!work) return -10;
   Resolved r;
-  int rc = resolve(o, &r);
+  int rc = resolve(o, &r, m, n);
   if (rc) return rc;
   const LsLayout L = ls_layout(m, n, nrhs, r);
   if (work_bytes < L.total) return TQR_E_WORKSPACE;
@@ -812,13 +895,15 @@ size_t tqr_lstsq_batched_work_size(int32_t count, const int64_t *m, const int64_
     ibs[0] = x.ib;
   }
   size_t best = 0;
+  const int tree_opt = x.tree;
+  if (x.tree == TQR_AUTO) x.tree = TQR_GRASAP;  // per-problem choice below; nb from opts
   for (int c = 0; c < nc; c++) {
     x.nb = nbs[c];
     x.ib = ibs[c];
     Resolved r;
     if (resolve(&x, &r)) return 0;
-    const BatchKey kf = batch_key(PK_LSTSQ, count, m, n, nrhs, r, x.tree);
-    const BatchKey ks = batch_key(PK_SNE, count, m, n, nrhs, r, x.tree);
+    const BatchKey kf = batch_key(PK_LSTSQ, count, m, n, nrhs, r, tree_opt);
+    const BatchKey ks = batch_key(PK_SNE, count, m, n, nrhs, r, tree_opt);
     best = std::max(best, batch_layout(count, m, n, nrhs, r, kf, ks).total);
   }
   return best;
@@ -839,9 +924,11 @@ int tqr_lstsq_batched(int32_t count, const int64_t *m, const int64_t *n, int64_t
   if (!work) return -11;
   tqr_opts d;
   tqr_default_opts(&d);
-  const int tree_opt = o ? o->tree : d.tree;
+  tqr_opts oc = o ? *o : d;
+  const int tree_opt = oc.tree;
+  if (oc.tree == TQR_AUTO) oc.tree = TQR_GRASAP;  // per-problem choice in batch_key; nb from opts
   Resolved r;
-  rc = resolve(o, &r);
+  rc = resolve(&oc, &r);
   if (rc) return rc;
   const bool mixed = r.update_dtype != TQR_F64;
   const BatchKey kf = batch_key(PK_LSTSQ, count, m, n, nrhs, r, tree_opt);
@@ -1030,6 +1117,104 @@ int tqr_autotune_batched(int32_t count, const int64_t *m, const int64_t *n, int6
   return TQR_OK;
 }
 
+int32_t tqr_mlp_params(void) { return kMlpParams; }
+int32_t tqr_mlp_features(void) { return kMlpFeatures; }
+
+int tqr_mlp_features_of(int64_t m, int64_t n, int32_t nb, int32_t tree, int32_t batch, float *out) {
+  if (m < 1 || n < 1) return -1;
+  if (nb < 1) return -3;
+  if (!out) return -6;
+  return mlp_features(m, n, nb, tree, batch, out);
+}
+
+size_t tqr_mlp_work_size(int64_t batch) { return batch < 1 ? 0 : mlp_work_bytes(batch); }
+
+int tqr_mlp_forward(const float *params, const float *X, int64_t batch, float *y, hipStream_t stream) {
+  if (!params) return -1;
+  if (!X) return -2;
+  if (batch < 1) return -3;
+  if (!y) return -4;
+  return mlp_forward(params, X, batch, y, stream) == hipSuccess ? TQR_OK : TQR_E_HIP;
+}
+
+int tqr_mlp_grad(const float *params, const float *X, const float *target, int64_t batch, float *grad,
+                 float *loss, void *work, size_t work_bytes, hipStream_t stream) {
+  if (!params) return -1;
+  if (!X) return -2;
+  if (!target) return -3;
+  if (batch < 1) return -4;
+  if (!grad) return -5;
+  if (!work) return -7;
+  if (work_bytes < mlp_work_bytes(batch)) return TQR_E_WORKSPACE;
+  return mlp_grad(params, X, target, batch, grad, loss, work, stream) == hipSuccess ? TQR_OK : TQR_E_HIP;
+}
+
+int tqr_mlp_adam(float *params, const float *grad, float *m1, float *m2, int64_t step, float lr,
+                 hipStream_t stream) {
+  if (!params) return -1;
+  if (!grad) return -2;
+  if (!m1) return -3;
+  if (!m2) return -4;
+  if (step < 1) return -5;
+  return mlp_adam(params, grad, m1, m2, step, lr, stream) == hipSuccess ? TQR_OK : TQR_E_HIP;
+}
+
+int tqr_mlp_fit(float *params, const float *X, const float *target, int64_t batch, int32_t epochs, float lr,
+                float *loss_hist, void *work, size_t work_bytes, hipStream_t stream) {
+  if (!params) return -1;
+  if (!X) return -2;
+  if (!target) return -3;
+  if (batch < 1) return -4;
+  if (epochs < 0) return -5;
+  if (!work) return -8;
+  if (work_bytes < mlp_work_bytes(batch)) return TQR_E_WORKSPACE;
+  // work: per-sample gradients and errors (used by mlp_grad), then the
+  // summed gradient and Adam's two moment vectors
+  float *grad = static_cast<float *>(work) + (size_t)batch * kMlpParams + (size_t)batch;
+  float *m1 = grad + kMlpParams;
+  float *m2 = m1 + kMlpParams;
+  if (mlp_zero(m1, 2 * (int64_t)kMlpParams, stream) != hipSuccess) return TQR_E_HIP;
+  for (int32_t e = 0; e < epochs; e++) {
+    if (mlp_grad(params, X, target, batch, grad, loss_hist ? loss_hist + e : nullptr, work, stream) != hipSuccess)
+      return TQR_E_HIP;
+    if (mlp_adam(params, grad, m1, m2, e + 1, lr, stream) != hipSuccess) return TQR_E_HIP;
+  }
+  return TQR_OK;
+}
+
+int tqr_set_selector(const float *params) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_sel.cache.clear();
+  if (!params) {
+    if (g_sel.params) hipFree(g_sel.params);
+    if (g_sel.scratch) hipFree(g_sel.scratch);
+    g_sel.params = nullptr;
+    g_sel.scratch = nullptr;
+    g_sel.dev = -1;
+    return TQR_OK;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TQR_E_HIP;
+  if (!g_sel.params && hipMalloc(&g_sel.params, kMlpParams * sizeof(float)) != hipSuccess) return TQR_E_NOMEM;
+  if (!g_sel.scratch && hipMalloc(&g_sel.scratch, 1024 * (kMlpFeatures + 1) * sizeof(float)) != hipSuccess)
+    return TQR_E_NOMEM;
+  if (hipMemcpy(g_sel.params, params, kMlpParams * sizeof(float), hipMemcpyDeviceToDevice) != hipSuccess)
+    return TQR_E_HIP;
+  g_sel.dev = dev;
+  return TQR_OK;
+}
+
+int tqr_select(int64_t m, int64_t n, int32_t batch, int32_t *tree, int32_t *nb, int32_t *ib) {
+  if (m < 1 || n < 1 || n > m) return -1;
+  int t, b, i;
+  const int rc = select_cfg(m, n, batch, &t, &b, &i);
+  if (rc) return rc;
+  if (tree) *tree = t;
+  if (nb) *nb = b;
+  if (ib) *ib = i;
+  return TQR_OK;
+}
+
 int64_t tqr_tree_list(int32_t tree, int32_t p, int32_t q, int32_t param, int32_t *i_out,
                       int32_t *piv_out, int32_t *k_out, int64_t cap) {
   if (p < 1 || q < 1 || q > p) return -2;
@@ -1069,7 +1254,7 @@ int64_t tqr_tree_cp(int32_t tree, int32_t p, int32_t q, int32_t param, int32_t k
 int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, int64_t *nedges) {
   if (m < 1 || n < 1 || n > m) return -1;
   Resolved r;
-  int rc = resolve(o, &r);
+  int rc = resolve(o, &r, m, n);
   if (rc) return rc;
   auto hp = host_plan(make_key(PK_FACTOR, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), 0, r));
   if (ntasks) *ntasks = (int64_t)hp->g.tasks.size();
@@ -1112,7 +1297,7 @@ int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_
   if (m < 1 || n < 1 || n > m) return -1;
   if (kind < PK_FACTOR || kind > PK_SNE) return -4;
   Resolved r;
-  int rc = resolve(o, &r);
+  int rc = resolve(o, &r, m, n);
   if (rc) return rc;
   auto hp = host_plan(make_key(kind, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), kind == PK_FACTOR ? 0 : nrhs, r));
   const int64_t nt = (int64_t)hp->g.tasks.size();
@@ -1137,7 +1322,7 @@ int tqr_debug_succ(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_o
   if (m < 1 || n < 1 || n > m) return -1;
   if (kind < PK_FACTOR || kind > PK_SNE) return -4;
   Resolved r;
-  int rc = resolve(o, &r);
+  int rc = resolve(o, &r, m, n);
   if (rc) return rc;
   auto hp = host_plan(make_key(kind, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), kind == PK_FACTOR ? 0 : nrhs, r));
   if ((int64_t)hp->g.succ.size() > cap) return -1;
