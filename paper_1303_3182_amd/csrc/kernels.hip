@@ -635,8 +635,8 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
   constexpr int RG = NT / IB;
   constexpr int PRU = (MODE == M_UNM) ? NB / RG : (NB + IB) / RG;
   constexpr int UH = ((MODE == M_TT) ? 2 * IB : IB) / RG;  // head slots
-  constexpr int UT = IB / RG;                              // slots of panel rows < IB
   constexpr int NBLK = NB / IB;
+  constexpr int KOUT = (128 / IB) < NBLK ? (128 / IB) : NBLK;  // blocks per outer block
   constexpr int LDV = Smem<NB, IB, WC>::LDV;
   constexpr int LDT = Smem<NB, IB, WC>::LDT;
   const int tid = opaque_tid();
@@ -695,6 +695,28 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
       sig_n = group_sum<RG>(sig_n);
       alpha_n = group_sum<RG>(alpha_n);
     }
+    // row jt of the block's T, built during the steps: lane g keeps
+    // T(jt, g + RG q) in trow[q]; T(r, j) = tau_j (r = j),
+    // -tau_j sum_{r <= c < j} T(r, c) Ys(c, j) (r < j), 0 (r > j), with
+    // Ys(c, j) = v_c^T v_j from the dot products of step j.  The groups of
+    // the finished columns (jt < j), idle otherwise, form T(jt, j-1) at
+    // step j, once the barrier has made Ys(., j-1) complete.
+    double trow[IB / RG];
+#pragma unroll
+    for (int q = 0; q < IB / RG; q++) trow[q] = 0.0;
+    auto t_column = [&](int jp) {
+      double sp = 0.0;
+#pragma unroll
+      for (int q = 0; q < IB / RG; q++) {
+        const int c = g + RG * q;
+        sp += zmask(trow[q] * sm.Ys[c * LDT + jp], c >= jt && c < jp);
+      }
+      const double ssum = group_sum<RG>(sp);
+      const double tj = sm.tau[jp];
+      const double v = (jt == jp) ? tj : -tj * ssum;
+#pragma unroll
+      for (int q = 0; q < IB / RG; q++) trow[q] = (g + RG * q == jp) ? v : trow[q];
+    };
     __syncthreads();
 
     for (int j = 0; j < IB; j++) {
@@ -703,7 +725,7 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
         const double sig = sig_n, alpha = alpha_n;
         double tau = 0.0, beta = alpha, scale = 0.0;
         if (sig != 0.0) {
-          const double nrm = hsqrt(alpha * alpha + sig);
+          const double nrm = hsqrt(fma(alpha, alpha, sig));
           beta = (alpha >= 0.0) ? -nrm : nrm;
           tau = (beta - alpha) * hrcp(beta);
           scale = hrcp(alpha - beta);
@@ -754,11 +776,15 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
             sig_n = group_sum<RG>(sg + sg2);
             alpha_n = group_sum<RG>(al);
           }
-        } else if (g == 0) {
-          sm.Ys[jt * LDT + j] = dot;  // v_jt^T v_j, jt < j
+        } else {
+          if (g == 0) sm.Ys[jt * LDT + j] = dot;  // v_jt^T v_j, jt < j
+          if (j > 0) t_column(j - 1);
         }
       }
     }
+    __syncthreads();  // Ys(., IB-1) and tau complete
+    t_column(IB - 1);
+
 
     // ---- write the panel back and stage V_b for the trailing update
 #pragma unroll
@@ -779,42 +805,37 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
       }
     }
     __syncthreads();
-    // ---- T of the block: T(r,r) = tau_r, T(r,j) = -tau_j sum_{c<j} T(r,c) Ys(c,j).
-    //      Row r is computed by the RG lanes of panel column r; lane g keeps
-    //      T(r, g + RG q) in register trow[q] (the reduction leaves the sum
-    //      in every lane of the group), so no lane reads what another lane
-    //      of its wave wrote to LDS without a barrier in between.
-    {
-      const int r = jt;
-      double trow[IB / RG];
+    // ---- the block's T (row jt in trow) to LDS for the trailing update
 #pragma unroll
-      for (int q = 0; q < IB / RG; q++) trow[q] = 0.0;
-#pragma unroll
-      for (int jj = 0; jj < IB; jj++) {
-        double sp = 0.0;
-#pragma unroll
-        for (int q = 0; q < IB / RG; q++) {
-          const int cc = g + RG * q;
-          sp += zmask(trow[q] * sm.Ys[cc * LDT + jj], cc >= r && cc < jj);
-        }
-        const double ssum = group_sum<RG>(sp);
-        const double tj = sm.tau[jj];
-        const double v = (r == jj) ? tj : ((r < jj) ? -tj * ssum : 0.0);
-        if (g == jj % RG) trow[jj / RG] = v;
-        if (g == 0) sm.TL[0][jj * LDT + r] = v;
-      }
-    }
+    for (int q = 0; q < IB / RG; q++) sm.TL[0][(g + RG * q) * LDT + jt] = trow[q];
     __syncthreads();
     for (int idx = tid; idx < IB * IB; idx += NT) {
       const int cc = idx / IB, r = idx % IB;
       Tout[(col0 + cc) * IB + r] = sm.TL[0][cc * LDT + r];
     }
-    // ---- trailing update of the tile's remaining columns with block b
-    for (int cs = col0 + IB; cs < ncols; cs += CHUNK) {
-      const int nc = min(CHUNK, ncols - cs);
-      apply_chunk<NB, IB, WC, MODE>(nullptr, 0, vrows, ncols, nullptr,
-                                    (MODE == M_UNM) ? nullptr : R1 + cs * ldr, ldr, Vt + cs * ldv,
-                                    ldv, vrows, nc, b, b + 1, true, false, sm);
+    // ---- trailing update, two levels: block b is applied at once (from
+    //      LDS) only to the rest of its outer block of KOUT blocks; when an
+    //      outer block is complete, its KOUT blocks are applied together to
+    //      every column after it (V and T reloaded, double-buffered), so the
+    //      far columns see few, long MFMA passes instead of one per block.
+    {
+      const int oend = min(ncols, (b / KOUT + 1) * KOUT * IB);
+      for (int cs = col0 + IB; cs < oend; cs += CHUNK) {
+        const int nc = min(CHUNK, oend - cs);
+        apply_chunk<NB, IB, WC, MODE>(nullptr, 0, vrows, ncols, nullptr,
+                                      (MODE == M_UNM) ? nullptr : R1 + cs * ldr, ldr, Vt + cs * ldv,
+                                      ldv, vrows, nc, b, b + 1, true, false, sm);
+      }
+      if ((b % KOUT == KOUT - 1 || b == NBLK - 1) && oend < ncols) {
+        const int b0 = (b / KOUT) * KOUT;
+        __syncthreads();  // Vt, R1 and Tout written by every thread
+        for (int cs = oend; cs < ncols; cs += CHUNK) {
+          const int nc = min(CHUNK, ncols - cs);
+          apply_chunk<NB, IB, WC, MODE>(Vt, ldv, vrows, ncols, Tout,
+                                        (MODE == M_UNM) ? nullptr : R1 + cs * ldr, ldr, Vt + cs * ldv,
+                                        ldv, vrows, nc, b0, b + 1, false, false, sm);
+        }
+      }
     }
     __syncthreads();
   }
