@@ -92,10 +92,29 @@ def timed(fn, steps, warmup, torch, T):
     return (t1 - t0) / steps * 1e3, kern_ms / max(launches, 1), launches / steps
 
 
-def roofline(flops, kernel_ms, kernel):
+def recorded_traffic(record):
+    """HBM bytes per executor launch from a committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE measurement (profiles/traffic_*.json), or None when the
+    sources of the measured kernel have changed since (their SHA-256 is
+    recorded with the counts)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", record)
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        return rec["bytes_total"] if h.hexdigest() == rec["sha256"] else None
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def roofline(flops, kernel_ms, kernel, traffic=None):
     achieved = flops / (kernel_ms / 1e3) / 1e12
     return {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_MFMA, "traffic": None, "kernel": kernel}
+            "frac": achieved / PEAK_FP64_MFMA, "traffic": traffic, "kernel": kernel}
 
 
 def base_line(args, value, ms, dtype, config):
@@ -155,8 +174,10 @@ def run_tall(args, np, torch, T, synth):
     out["executor_ms"] = kms
     out["ls_backward_error"] = be
     out["mixed_precision"] = mixed
+    default = (m, n, nb, args.ib, args.tree, args.kernels, args.stripes) == (16384, 2048, 256, 32, "grasap", "tt", 0)
     out["roofline"] = roofline(qr_flops(m, n), kms,
-                               "exec_persistent (least-squares task graph: factor, Q^T b, R x = c)")
+                               "exec_persistent (least-squares task graph: factor, Q^T b, R x = c)",
+                               recorded_traffic("traffic_lstsq_16384x2048_nb256.json") if default else None)
     if not args.no_cpu_baseline:
         c = args.cpu_sample_cols
         log("cpu baseline: oracle on a %d-column sample" % c)
