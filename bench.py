@@ -3,13 +3,15 @@
 
 Default workload (--workload tall): FP64 least squares on a tall-skinny
 matrix, m = 16384, n = 2048, tile nb = 256 (64 x 8 tiles), entries i.i.d.
-N(0,1) (seeded, synthetic), GrASAP elimination tree, TT kernels.  One step
+N(0,1) (seeded, synthetic), Greedy elimination tree, TT kernels.  One step
 is the whole hot path on one batch: tqr_lstsq, i.e. copy A and b into the
 workspace, then one persistent executor launch that factors A = QR, applies
 Q^T to b as the factorization proceeds, and back-substitutes
 R x = (Q^T b)(1:n) (elimination list and task graph are cached after the
 first call).  The same solve is then timed with FP32 and BF16 trailing
-updates plus FP64 refinement to the FP64 backward error.
+updates plus FP64 refinement to the FP64 backward error, and with each of
+the five trees (FlatTree, BinaryTree, Fibonacci, Greedy, GrASAP) on the
+same input.
 
 Other workloads (each prints its own JSON line):
   --workload square   8192 x 8192 systems A = U diag(sigma) V^T with Haar U,
@@ -92,7 +94,7 @@ def timed(fn, steps, warmup, torch, T):
     return (t1 - t0) / steps * 1e3, kern_ms / max(launches, 1), launches / steps
 
 
-def recorded_traffic(record):
+def recorded_traffic(record, workload):
     """HBM bytes per executor launch from a committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE measurement (profiles/traffic_*.json), or None when the
     sources of the measured kernel have changed since (their SHA-256 is
@@ -106,7 +108,8 @@ def recorded_traffic(record):
         for src in rec["sources"]:
             with open(os.path.join(ROOT, src), "rb") as f:
                 h.update(f.read())
-        return rec["bytes_total"] if h.hexdigest() == rec["sha256"] else None
+        same = h.hexdigest() == rec["sha256"] and rec["workload"] == workload
+        return rec["bytes_total"] if same else None
     except (OSError, KeyError, ValueError):
         return None
 
@@ -174,10 +177,23 @@ def run_tall(args, np, torch, T, synth):
     out["executor_ms"] = kms
     out["ls_backward_error"] = be
     out["mixed_precision"] = mixed
-    default = (m, n, nb, args.ib, args.tree, args.kernels, args.stripes) == (16384, 2048, 256, 32, "grasap", "tt", 0)
+    if not args.no_tree_compare:
+        # the five trees of the thesis on identical inputs (FP64 lstsq, same nb)
+        trees = {}
+        for tr in ["flat", "binary", "fibonacci", "greedy", "grasap"]:
+            ot = T.default_opts(nb=nb, ib=args.ib, tree=tr, kernels=args.kernels, stripes=args.stripes)
+            wt = T.lstsq_workspace(m, n, 1, ot, dev)
+            tms, tkms, _ = timed(lambda: T.lstsq(A, b, ot, X=X, work=wt, info=info), 2, 1, torch, T)
+            cp = T.tqr_tree_cp(tr, -(-m // nb), -(-n // nb), 0, T.TT if args.kernels == "tt" else T.HYBRID)
+            trees[tr] = {"ms_per_step": tms, "value": qr_flops(m, n) / (tms / 1e3) / 1e12,
+                         "critical_path_units": cp, "ls_backward_error": backward_error(X[:, 0].cpu().numpy())}
+            log("tree %s: %.2f ms (critical path %d units)" % (tr, tms, cp))
+        out["trees"] = trees
+    wkey = "tall %dx%d nb=%d ib=%d %s %s lstsq" % (m, n, nb, args.ib, args.tree, args.kernels)
     out["roofline"] = roofline(qr_flops(m, n), kms,
                                "exec_persistent (least-squares task graph: factor, Q^T b, R x = c)",
-                               recorded_traffic("traffic_lstsq_16384x2048_nb256.json") if default else None)
+                               recorded_traffic("traffic_lstsq_16384x2048_nb256.json", wkey)
+                               if args.stripes == 0 else None)
     if not args.no_cpu_baseline:
         c = args.cpu_sample_cols
         log("cpu baseline: oracle on a %d-column sample" % c)
@@ -303,7 +319,9 @@ def main():
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--nb", type=int, default=256)
     ap.add_argument("--ib", type=int, default=32)
-    ap.add_argument("--tree", default="grasap")
+    ap.add_argument("--tree", default="greedy")
+    ap.add_argument("--no-tree-compare", action="store_true",
+                    help="skip timing the five trees on the tall-skinny workload")
     ap.add_argument("--kernels", default="tt")
     ap.add_argument("--stripes", type=int, default=0)
     ap.add_argument("--cpu-sample-cols", type=int, default=256)
