@@ -189,6 +189,33 @@ def run_tall(args, np, torch, T, synth):
                          "critical_path_units": cp, "ls_backward_error": backward_error(X[:, 0].cpu().numpy())}
             log("tree %s: %.2f ms (critical path %d units)" % (tr, tms, cp))
         out["trees"] = trees
+        # beyond the stated configuration: the learned selector's choice of
+        # (tree, nb) for this shape, and the best of a small grid
+        from paper_1303_3182_amd import selector as S
+        tuned = {}
+        if S.load_selector() is not None:
+            ot = T.default_opts(tree="auto", kernels=args.kernels)
+            tid, snb, sib = S.select(m, n)
+            wt = T.lstsq_workspace(m, n, 1, ot, dev)
+            tms, _, _ = timed(lambda: T.lstsq(A, b, ot, X=X, work=wt, info=info), 3, 1, torch, T)
+            name = [k for k, v in T.TREES.items() if v == tid][0]
+            tuned["selector"] = {"tree": name, "nb": snb, "ib": sib, "ms_per_step": tms,
+                                 "value": qr_flops(m, n) / (tms / 1e3) / 1e12}
+            S.set_selector(None)
+        best = None
+        for gnb in (128, 256):
+            for gtr in ("greedy", "fibonacci"):
+                for gk in ("tt", "hybrid"):
+                    og = T.default_opts(nb=gnb, tree=gtr, kernels=gk)
+                    wg = T.lstsq_workspace(m, n, 1, og, dev)
+                    gms, _, _ = timed(lambda: T.lstsq(A, b, og, X=X, work=wg, info=info), 3, 1, torch, T)
+                    if best is None or gms < best["ms_per_step"]:
+                        best = {"nb": gnb, "tree": gtr, "kernels": gk, "ms_per_step": gms,
+                                "value": qr_flops(m, n) / (gms / 1e3) / 1e12,
+                                "ls_backward_error": backward_error(X[:, 0].cpu().numpy())}
+        tuned["best_of_grid"] = best
+        log("tuned: %s" % json.dumps(tuned))
+        out["tuned"] = tuned
     wkey = "tall %dx%d nb=%d ib=%d %s %s lstsq" % (m, n, nb, args.ib, args.tree, args.kernels)
     out["roofline"] = roofline(qr_flops(m, n), kms,
                                "exec_persistent (least-squares task graph: factor, Q^T b, R x = c)",
