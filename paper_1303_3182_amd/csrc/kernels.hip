@@ -1012,13 +1012,44 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// LDS copy of rows [0, nr) of nc columns of a column-major block:
+// dst[cc * NB + row] = src[cc * ld + row].  Each wave takes every fourth
+// column, GV_BT columns per batch, and issues the whole batch's loads
+// (clamped in bounds, so unconditional) before storing any.
+template <int NB>
+__device__ __forceinline__ void stage_cols(const double *__restrict__ src, int64_t ld, int nr, int nc,
+                                           double *dst) {
+  constexpr int U = (NB + 63) / 64;
+  constexpr int NW = NT / 64;
+  constexpr int BT = 8;
+  if (nr <= 0 || nc <= 0) return;
+  const int tid = opaque_tid();
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  for (int c0 = w; c0 < nc; c0 += NW * BT) {
+    double v[BT][U];
+#pragma unroll
+    for (int b = 0; b < BT; b++)
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        v[b][u] = src[(int64_t)min(c0 + NW * b, nc - 1) * ld + min(u * 64 + lane, nr - 1)];
+#pragma unroll
+    for (int b = 0; b < BT; b++)
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int cc = c0 + NW * b, row = u * 64 + lane;
+        if (cc < nc && row < nr) dst[cc * NB + row] = v[b][u];
+      }
+  }
+}
+
 // Back-substitution R x = y for a few right-hand sides: one wave per
 // column (two at most), each lane holding rows lane, lane + 64, ... in
 // registers.  R's columns are staged in LDS 64 at a time (all rows above
 // them).  Row r, from the bottom, is finished by its owner lane and
 // broadcast with a lane read; every lane then removes its contribution from
 // the rows above.  A chain of nk short steps, instead of the blocked
-// solve's serial per-column loops.
+// solve's serial per-column loops; the diagonal's reciprocals are taken
+// while a block is staged, so the chain multiplies instead of dividing.
 template <int NB, int IB, int WC>
 __device__ __forceinline__ void trsm_waves(const double *R, int64_t ldr, int nk, double *X, int64_t ldx,
                                            int ncols, int row0, int32_t *singular, Smem<NB, IB, WC> &sm) {
@@ -1027,6 +1058,8 @@ __device__ __forceinline__ void trsm_waves(const double *R, int64_t ldr, int nk,
   constexpr int CPW = 2;             // columns per wave
   static_assert(2 * Smem<NB, IB, WC>::VSZ >= CB * NB, "LDS too small for a column block of R");
   double *Ls = &sm.VL[0][0];         // VL[0] and VL[1] are contiguous
+  double *rinv = &sm.vbuf[0][0];     // reciprocals of the block's diagonal
+  static_assert(NB + IB >= CB, "vbuf too small for the diagonal's reciprocals");
   const int tid = opaque_tid();
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -1046,10 +1079,8 @@ __device__ __forceinline__ void trsm_waves(const double *R, int64_t ldr, int nk,
     if (c0 >= nk) continue;
     const int c1 = min(nk, c0 + CB);
     __syncthreads();  // the previous block's readers are done
-    for (int idx = tid; idx < (c1 - c0) * c1; idx += NT) {
-      const int cc = idx / c1, row = idx % c1;
-      Ls[cc * NB + row] = R[(c0 + cc) * ldr + row];
-    }
+    stage_cols<NB>(R + (int64_t)c0 * ldr, ldr, c1, c1 - c0, Ls);
+    if (tid < c1 - c0) rinv[tid] = 1.0 / R[(int64_t)(c0 + tid) * ldr + c0 + tid];
     __syncthreads();
     double uc[U], un[U];
     auto load_col = [&](int l, double *dst) {
@@ -1065,7 +1096,7 @@ __device__ __forceinline__ void trsm_waves(const double *R, int64_t ldr, int nk,
       if (d == 0.0 && w == 0 && lane == 0) atomicMin(singular, row0 + r + 1);
 #pragma unroll
       for (int c = 0; c < CPW; c++) {
-        const double xr = readlane_d(y[c][ub], l) / d;
+        const double xr = readlane_d(y[c][ub], l) * rinv[l];
 #pragma unroll
         for (int u = 0; u <= ub; u++) {
           if (u < ub)
@@ -1095,11 +1126,107 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
+// C(r, c) -= sum_kc R(r, kc) X(kc, c)  (trans: R(kc, r)) for at most GV_COLS
+// right-hand-side columns: a streaming matrix-vector product (the MFMA tile
+// product would spend 16 columns of work on each useful one).  X is staged
+// in LDS; R streams from global memory GV_BT columns per wave at a time, all
+// loads issued before any is consumed (a single CU needs many bytes in flight
+// to approach its share of HBM bandwidth).  Not transposed: wave w takes
+// columns kc = w mod 4 with lanes down the rows, and the four waves' partial
+// sums meet in LDS.  Transposed: wave w takes columns r = w mod 4 of R with
+// lanes down each column, and a wave reduction per right-hand side.
+constexpr int GV_COLS = 8;
+constexpr int GV_BT = 8;
+template <int NB, int IB, int WC>
+__device__ __forceinline__ void gemv_tile(const double *R, int64_t ldr, int nk, const double *X, int64_t ldx,
+                                          double *C, int64_t ldc, int crows, int ncols, bool trans,
+                                          Smem<NB, IB, WC> &sm) {
+  constexpr int U = (NB + 63) / 64;
+  constexpr int NW = NT / 64;
+  static_assert(2 * Smem<NB, IB, WC>::VSZ >= NB * GV_COLS + NW * GV_COLS * NB, "LDS too small for gemv");
+  double *xs = &sm.VL[0][0];        // X block, xs[c * NB + kc]
+  double *red = xs + NB * GV_COLS;  // partial sums, red[(w * GV_COLS + c) * NB + r]
+  const int tid = opaque_tid();
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  if (nk <= 0 || crows <= 0 || ncols <= 0) return;
+  __syncthreads();  // earlier users of the LDS are done
+  for (int c = 0; c < ncols; c++)
+    for (int kc = tid; kc < nk; kc += NT) xs[c * NB + kc] = X[c * ldx + kc];
+  __syncthreads();
+  double v[GV_BT][U];
+  if (!trans) {
+    double acc[GV_COLS][U];
+#pragma unroll
+    for (int c = 0; c < GV_COLS; c++)
+#pragma unroll
+      for (int u = 0; u < U; u++) acc[c][u] = 0.0;
+    for (int k0 = w; k0 < nk; k0 += NW * GV_BT) {
+#pragma unroll
+      for (int b = 0; b < GV_BT; b++)
+#pragma unroll
+        for (int u = 0; u < U; u++)
+          v[b][u] = R[(int64_t)min(k0 + NW * b, nk - 1) * ldr + min(u * 64 + lane, crows - 1)];
+#pragma unroll
+      for (int b = 0; b < GV_BT; b++) {
+        const int kc = k0 + NW * b;
+        if (kc < nk) {
+#pragma unroll
+          for (int c = 0; c < GV_COLS; c++)
+            if (c < ncols) {
+              const double xv = xs[c * NB + kc];
+#pragma unroll
+              for (int u = 0; u < U; u++) acc[c][u] = fma(v[b][u], xv, acc[c][u]);
+            }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < GV_COLS; c++)
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (c < ncols && u * 64 + lane < NB) red[(w * GV_COLS + c) * NB + u * 64 + lane] = acc[c][u];
+    __syncthreads();
+    for (int c = 0; c < ncols; c++)
+      for (int r = tid; r < crows; r += NT) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; q++) sum += red[(q * GV_COLS + c) * NB + r];
+        C[c * ldc + r] -= sum;
+      }
+    return;
+  }
+  for (int r0 = w; r0 < crows; r0 += NW * GV_BT) {
+#pragma unroll
+    for (int b = 0; b < GV_BT; b++)
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int kc = u * 64 + lane;
+        v[b][u] = zmask(R[(int64_t)min(r0 + NW * b, crows - 1) * ldr + min(kc, nk - 1)], kc < nk);
+      }
+#pragma unroll
+    for (int b = 0; b < GV_BT; b++) {
+      const int r = r0 + NW * b;
+      if (r < crows) {
+#pragma unroll
+        for (int c = 0; c < GV_COLS; c++)
+          if (c < ncols) {
+            double p = 0.0;
+#pragma unroll
+            for (int u = 0; u < U; u++) p = fma(v[b][u], xs[c * NB + min(u * 64 + lane, nk - 1)], p);
+            const double sum = wave_sum(p);
+            if (lane == 0) C[c * ldc + r] -= sum;
+          }
+      }
+    }
+  }
+}
+
 // Forward substitution R^T z = y (R upper triangular, so R^T is lower) for
 // right-hand sides in groups of two columns per wave, lanes holding rows as
 // in trsm_waves.  Left-looking: row r needs column r of R above the
 // diagonal, dotted with the solved part of z (a wave reduction), which keeps
-// R's columns contiguous in LDS exactly as the backward solve stages them.
+// R's columns contiguous in LDS exactly as the backward solve stages them
+// (with the diagonal's reciprocals, as there).
 template <int NB, int IB, int WC>
 __device__ __forceinline__ void trsmt_waves(const double *R, int64_t ldr, int nk, double *X, int64_t ldx,
                                             int ncols, int row0, int32_t *singular, Smem<NB, IB, WC> &sm) {
@@ -1107,6 +1234,7 @@ __device__ __forceinline__ void trsmt_waves(const double *R, int64_t ldr, int nk
   constexpr int CB = NB < 64 ? NB : 64;
   constexpr int CPW = 2;
   double *Ls = &sm.VL[0][0];
+  double *rinv = &sm.vbuf[0][0];  // reciprocals of the block's diagonal
   const int tid = opaque_tid();
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -1128,10 +1256,8 @@ __device__ __forceinline__ void trsmt_waves(const double *R, int64_t ldr, int nk
       if (c0 < nk) {
         const int c1 = min(nk, c0 + CB);
         __syncthreads();
-        for (int idx = tid; idx < (c1 - c0) * c1; idx += NT) {
-          const int cc = idx / c1, row = idx % c1;
-          Ls[cc * NB + row] = R[(c0 + cc) * ldr + row];
-        }
+        stage_cols<NB>(R + (int64_t)c0 * ldr, ldr, c1, c1 - c0, Ls);
+        if (tid < c1 - c0) rinv[tid] = 1.0 / R[(int64_t)(c0 + tid) * ldr + c0 + tid];
         __syncthreads();
         for (int l = 0; l < c1 - c0; l++) {
           const int r = c0 + l;
@@ -1146,7 +1272,7 @@ __device__ __forceinline__ void trsmt_waves(const double *R, int64_t ldr, int nk
             double p = 0.0;
 #pragma unroll
             for (int u = 0; u <= ub; u++) p = fma(rv[u], z[c][u], p);  // z is zero from row r on
-            const double zr = (readlane_d(y[c][ub], l) - wave_sum(p)) / d;
+            const double zr = (readlane_d(y[c][ub], l) - wave_sum(p)) * rinv[l];
             z[c][ub] = (lane == l) ? zr : z[c][ub];
           }
         }
@@ -1209,6 +1335,13 @@ __device__ __forceinline__ void run_task(const Problem &a, const Task &t, Smem<N
       else if (kind == K_TRSMT)
         trsmt_waves<NB, IB, WC>(tileA(t.k, t.k), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
                                 a.ldb, nc, t.k * NB, a.singular, sm);
+      else if (kind == K_GEMM && nc <= GV_COLS)
+        gemv_tile<NB, IB, WC>(tileA(t.i, t.k), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
+                              a.ldb, Bc + (int64_t)cs * a.ldb + (int64_t)t.i * NB, a.ldb, NB, nc, false, sm);
+      else if (kind == K_GEMMT && nc <= GV_COLS)
+        gemv_tile<NB, IB, WC>(tileA(t.k, t.i), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
+                              a.ldb, Bc + (int64_t)cs * a.ldb + (int64_t)t.i * NB, a.ldb,
+                              (int)min((int64_t)NB, a.n - (int64_t)t.i * NB), nc, true, sm);
       else if (kind == K_GEMM)
         gemm_tile<NB, IB, WC>(tileA(t.i, t.k), lda, nkk, Bc + (int64_t)cs * a.ldb + (int64_t)t.k * NB,
                               a.ldb, Bc + (int64_t)cs * a.ldb + (int64_t)t.i * NB, a.ldb, NB, nc, false, sm);
