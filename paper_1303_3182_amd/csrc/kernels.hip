@@ -628,25 +628,43 @@ __device__ __forceinline__ void apply_chunk_lp(const double *__restrict__ V, int
 //   M_UNM: tile rows col0 + pr                       (head: the IB x IB diagonal block)
 //   M_TT : [R1 rows col0..col0+IB) [Vt rows col0..col0+IB) [Vt rows 0..col0)
 //   M_TS : [R1 rows col0..col0+IB) [Vt rows 0..NB)
-template <int NB, int IB, int WC, int MODE>
-__device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, double *R1,
-                                           int64_t ldr, int ncols, double *Tout,
-                                           Smem<NB, IB, WC> &sm) {
+// Panel rows of inner block b (the rest of the ordering is zero padding),
+// and the row slots per thread that hold them.
+template <int NB, int IB, int MODE>
+constexpr int panel_rows(int b) {
+  return (MODE == M_UNM) ? NB - b * IB : (MODE == M_TT ? 2 * IB + b * IB : IB + NB);
+}
+template <int NB, int IB, int MODE>
+constexpr int panel_slots(int b) {
   constexpr int RG = NT / IB;
   constexpr int PRU = (MODE == M_UNM) ? NB / RG : (NB + IB) / RG;
+  const int s = (panel_rows<NB, IB, MODE>(b) + RG - 1) / RG;
+  return s < PRU ? s : PRU;
+}
+
+// Inner block B of a panel kernel: factor columns [B*IB, (B+1)*IB) (which
+// the earlier blocks have updated), write the reflectors and R back, the
+// block's T to Tout, and leave V_B in VL[0] and T_B in TL[0] for the
+// trailing update.  Compiled per block, each thread carrying only the
+// PRU = panel_slots(B) row slots that hold the block's live panel rows
+// (TT: 2 IB + B IB rows, GEQRT: NB - B IB), not the whole tile's padding.
+template <int NB, int IB, int WC, int MODE, int B>
+__device__ __forceinline__ void panel_block(double *Vt, int64_t ldv, int vrows, double *R1,
+                                            int64_t ldr, int ncols, double *Tout,
+                                            Smem<NB, IB, WC> &sm) {
+  constexpr int RG = NT / IB;
+  constexpr int PRU = panel_slots<NB, IB, MODE>(B);
   constexpr int UH = ((MODE == M_TT) ? 2 * IB : IB) / RG;  // head slots
-  constexpr int NBLK = NB / IB;
-  constexpr int KOUT = (128 / IB) < NBLK ? (128 / IB) : NBLK;  // blocks per outer block
+  static_assert(PRU >= UH, "every block holds its head rows");
   constexpr int LDV = Smem<NB, IB, WC>::LDV;
   constexpr int LDT = Smem<NB, IB, WC>::LDT;
   const int tid = opaque_tid();
   const int jt = tid / RG;  // panel column of this thread
   const int g = tid % RG;
-
-  for (int b = 0; b < NBLK; b++) {
-    const int col0 = b * IB;
+  {
+    constexpr int col0 = B * IB;
     const int col = col0 + jt;
-    const int npr = (MODE == M_UNM) ? NB - col0 : (MODE == M_TT ? 2 * IB + col0 : IB + NB);
+    constexpr int npr = panel_rows<NB, IB, MODE>(B);
     const int colc = min(col, ncols - 1);
     const bool cok = col < ncols;
     // tile row of panel row pr, and which matrix it lives in (true: R1)
@@ -813,6 +831,31 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
       const int cc = idx / IB, r = idx % IB;
       Tout[(col0 + cc) * IB + r] = sm.TL[0][cc * LDT + r];
     }
+  }
+}
+
+// Runs panel_block<B> for the runtime block index b.
+template <int NB, int IB, int WC, int MODE, int B = 0>
+__device__ __forceinline__ void panel_block_at(int b, double *Vt, int64_t ldv, int vrows, double *R1,
+                                               int64_t ldr, int ncols, double *Tout,
+                                               Smem<NB, IB, WC> &sm) {
+  if (b == B) {
+    panel_block<NB, IB, WC, MODE, B>(Vt, ldv, vrows, R1, ldr, ncols, Tout, sm);
+    return;
+  }
+  if constexpr (B + 1 < NB / IB)
+    panel_block_at<NB, IB, WC, MODE, B + 1>(b, Vt, ldv, vrows, R1, ldr, ncols, Tout, sm);
+}
+
+template <int NB, int IB, int WC, int MODE>
+__device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, double *R1,
+                                           int64_t ldr, int ncols, double *Tout,
+                                           Smem<NB, IB, WC> &sm) {
+  constexpr int NBLK = NB / IB;
+  constexpr int KOUT = (128 / IB) < NBLK ? (128 / IB) : NBLK;  // blocks per outer block
+  for (int b = 0; b < NBLK; b++) {
+    const int col0 = b * IB;
+    panel_block_at<NB, IB, WC, MODE>(b, Vt, ldv, vrows, R1, ldr, ncols, Tout, sm);
     // ---- trailing update, two levels: block b is applied at once (from
     //      LDS) only to the rest of its outer block of KOUT blocks; when an
     //      outer block is complete, its KOUT blocks are applied together to
