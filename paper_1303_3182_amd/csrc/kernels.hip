@@ -1474,9 +1474,6 @@ __device__ __forceinline__ Task load_task(const Task *p) {
   return t;
 }
 
-__device__ __forceinline__ int ld_acquire(const int32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ int ld_relaxed(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1526,8 +1523,13 @@ __global__ __launch_bounds__(NT, 1) void exec_persistent(ExecArgs a) {
       if (h < a.ntasks) {
         const int64_t t0 = wall_clock64();
         for (;;) {
-          task = ld_acquire(&a.queue[h]);
-          if (task >= 0) break;
+          // relaxed polling: an acquire here would invalidate this XCD's L2
+          // at every poll, under every other workgroup's feet
+          task = ld_relaxed(&a.queue[h]);
+          if (task >= 0) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            break;
+          }
           if (ld_relaxed(&ctl->abort)) break;
           if (wall_clock64() - t0 > a.spin_limit) {
             __hip_atomic_store(&ctl->error, -1000, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1544,15 +1546,20 @@ __global__ __launch_bounds__(NT, 1) void exec_persistent(ExecArgs a) {
     // a scalar branch, so no lane can leave the loop while others stay in it.
     const int tid = __builtin_amdgcn_readfirstlane(sm.task);
     if (tid < 0) break;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // (thread 0's acquire before the barrier invalidated the caches this
+    // CU reads through; the barrier orders every wave's loads after it)
     const int64_t tstart = a.trace ? (int64_t)wall_clock64() : 0;
     {
       const Task t = load_task(a.tasks + tid);
       run_task<NB, IB, WC>(a.probs ? a.probs[t.prob] : a.prob, t, sm);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // Every wave's stores reach L2 before the barrier (a workgroup barrier
+    // alone does not wait for them); thread 0 then releases the task's
+    // results to the device with one L2 write-back.
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
     if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (a.trace && tid < a.trace_cap) {
         int64_t *tr = a.trace + 4 * (int64_t)tid;
         tr[0] = tstart;
@@ -1562,9 +1569,12 @@ __global__ __launch_bounds__(NT, 1) void exec_persistent(ExecArgs a) {
       }
       for (int e = a.succ_off[tid]; e < a.succ_off[tid + 1]; e++) {
         const int s = a.succ[e];
-        if (__hip_atomic_fetch_add(&a.indeg[s], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+        if (__hip_atomic_fetch_add(&a.indeg[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+          // the last predecessor forwards the others' releases to the
+          // consumer: acquire them, then release before the push
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
           const int slot = __hip_atomic_fetch_add(&ctl->tail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          st_release(&a.queue[slot], s);
+          __hip_atomic_store(&a.queue[slot], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
       __hip_atomic_fetch_add(&ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
