@@ -1509,6 +1509,9 @@ __global__ void exec_reset(ExecArgs a) {
 // successor whose count reaches zero is pushed.  Every task is pushed
 // exactly once, so a workgroup that pops slot h >= ntasks exits.  A spin
 // that exceeds spin_limit sets abort/error and every workgroup exits.
+// Memory ordering costs whole-L2 operations on this chip (an agent-scope
+// release writes back the XCD's L2, an acquire invalidates it), so each
+// task pays exactly one of each: no acquire while polling, none on push.
 template <int NB, int IB, int WC>
 __global__ __launch_bounds__(NT, 1) void exec_persistent(ExecArgs a) {
   __shared__ Smem<NB, IB, WC> sm;
@@ -1523,11 +1526,16 @@ __global__ __launch_bounds__(NT, 1) void exec_persistent(ExecArgs a) {
       if (h < a.ntasks) {
         const int64_t t0 = wall_clock64();
         for (;;) {
-          // relaxed polling: an acquire here would invalidate this XCD's L2
-          // at every poll, under every other workgroup's feet
-          task = ld_relaxed(&a.queue[h]);
-          if (task >= 0) {
+          // Relaxed polling (an acquire here would invalidate this XCD's L2
+          // at every poll, under every other workgroup's feet).  A popped
+          // task synchronises with all its predecessors at once: each
+          // released its results and then decremented indeg[task], so
+          // reading the final count of zero (the end of that chain of
+          // read-modify-writes) and then fencing acquires every one of them.
+          const int t = ld_relaxed(&a.queue[h]);
+          if (t >= 0 && ld_relaxed(&a.indeg[t]) == 0) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            task = t;
             break;
           }
           if (ld_relaxed(&ctl->abort)) break;
@@ -1570,9 +1578,6 @@ __global__ __launch_bounds__(NT, 1) void exec_persistent(ExecArgs a) {
       for (int e = a.succ_off[tid]; e < a.succ_off[tid + 1]; e++) {
         const int s = a.succ[e];
         if (__hip_atomic_fetch_add(&a.indeg[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1) {
-          // the last predecessor forwards the others' releases to the
-          // consumer: acquire them, then release before the push
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
           const int slot = __hip_atomic_fetch_add(&ctl->tail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_store(&a.queue[slot], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
