@@ -221,12 +221,20 @@ __device__ __forceinline__ double vmask(double v, int row, int col) {
 // layout, whose register s is exactly the B operand of the K-step covering
 // rows 4s..4s+3 of a 16-row block.  The reflectors and T are shared through
 // LDS.  With `prestaged`, VL/TL already hold block b0 (one block only).
-template <int NB, int IB, int WC, int MODE, bool FULL = false>
+// FB0 >= 0: the blocks are [FB0, FB1), fixed at compile time (b0, b1 are
+// ignored), and the block loop is unrolled, so each block's row range, and
+// with it which MFMAs run and which operands are loaded, is known to the
+// compiler and the loads are scheduled ahead across row blocks.
+template <int NB, int IB, int WC, int MODE, int FB0 = -1, int FB1 = -1>
 __device__ __forceinline__ void apply_chunk(const double *__restrict__ V, int64_t ldv, int vrows,
                                             int vcols, const double *__restrict__ Tf, double *C1,
                                             int64_t ldc1, double *C2, int64_t ldc2, int c2rows,
                                             int ncols, int b0, int b1, bool prestaged, bool dma,
                                             Smem<NB, IB, WC> &sm) {
+  if constexpr (FB0 >= 0) {
+    b0 = FB0;
+    b1 = FB1;
+  }
   constexpr int NRB = NB / 16;
   constexpr int NMB = IB / 16;
   constexpr int LDV = Smem<NB, IB, WC>::LDV;
@@ -289,14 +297,6 @@ __device__ __forceinline__ void apply_chunk(const double *__restrict__ V, int64_
     load_t(b0);
   }
 
-  // FULL (every block of the tile, b0 = 0, b1 = NB / IB): the block loop has
-  // a constant trip count and is unrolled, so each block's row range, and
-  // with it which MFMAs run and which operands are loaded, is known at
-  // compile time and the loads are scheduled ahead across row blocks
-  if (FULL) {
-    b0 = 0;
-    b1 = NB / IB;
-  }
   auto block = [&](const int b) {
     const int buf = prestaged ? 0 : ((b - b0) & 1);
     int rlo, rhi;
@@ -397,9 +397,9 @@ __device__ __forceinline__ void apply_chunk(const double *__restrict__ V, int64_
       }
     }
   };
-  if constexpr (FULL) {
+  if constexpr (FB0 >= 0) {
 #pragma unroll
-    for (int b = 0; b < NB / IB; b++) block(b);
+    for (int b = FB0; b < FB1; b++) block(b);
   } else {
     for (int b = b0; b < b1; b++) block(b);
   }
@@ -848,13 +848,50 @@ __device__ __forceinline__ void panel_block(double *Vt, int64_t ldv, int vrows, 
   }
 }
 
-// Runs panel_block<B> for the runtime block index b.
+// The trailing update of the tile after inner block B, two levels: block B
+// is applied at once (from LDS) only to the rest of its outer block of KOUT
+// blocks; when an outer block is complete, its KOUT blocks are applied
+// together to every column after it (V and T reloaded, double-buffered), so
+// the far columns see few, long MFMA passes instead of one per block.  The
+// block ranges are compile-time constants (see apply_chunk).
+template <int NB, int IB, int WC, int MODE, int B>
+__device__ __forceinline__ void panel_trailing(double *Vt, int64_t ldv, int vrows, double *R1,
+                                               int64_t ldr, int ncols, double *Tout,
+                                               Smem<NB, IB, WC> &sm) {
+  constexpr int NBLK = NB / IB;
+  constexpr int KOUT = (128 / IB) < NBLK ? (128 / IB) : NBLK;  // blocks per outer block
+  constexpr int col0 = B * IB;
+  const int oend = min(ncols, (B / KOUT + 1) * KOUT * IB);
+  for (int cs = col0 + IB; cs < oend; cs += CHUNK) {
+    const int nc = min(CHUNK, oend - cs);
+    apply_chunk<NB, IB, WC, MODE, B, B + 1>(nullptr, 0, vrows, ncols, nullptr,
+                                            (MODE == M_UNM) ? nullptr : R1 + cs * ldr, ldr, Vt + cs * ldv,
+                                            ldv, vrows, nc, B, B + 1, true, false, sm);
+  }
+  if constexpr (B % KOUT == KOUT - 1 || B == NBLK - 1) {
+    constexpr int F0 = (B / KOUT) * KOUT;
+    if (oend < ncols) {
+      __syncthreads();  // Vt, R1 and Tout written by every thread
+      for (int cs = oend; cs < ncols; cs += CHUNK) {
+        const int nc = min(CHUNK, ncols - cs);
+        apply_chunk<NB, IB, WC, MODE, F0, B + 1>(Vt, ldv, vrows, ncols, Tout,
+                                                 (MODE == M_UNM) ? nullptr : R1 + cs * ldr, ldr,
+                                                 Vt + cs * ldv, ldv, vrows, nc, F0, B + 1, false, false, sm);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Runs inner block b (factorization and trailing update) with b fixed at
+// compile time.
 template <int NB, int IB, int WC, int MODE, int B = 0>
 __device__ __forceinline__ void panel_block_at(int b, double *Vt, int64_t ldv, int vrows, double *R1,
                                                int64_t ldr, int ncols, double *Tout,
                                                Smem<NB, IB, WC> &sm) {
   if (b == B) {
     panel_block<NB, IB, WC, MODE, B>(Vt, ldv, vrows, R1, ldr, ncols, Tout, sm);
+    panel_trailing<NB, IB, WC, MODE, B>(Vt, ldv, vrows, R1, ldr, ncols, Tout, sm);
     return;
   }
   if constexpr (B + 1 < NB / IB)
@@ -865,37 +902,7 @@ template <int NB, int IB, int WC, int MODE>
 __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, double *R1,
                                            int64_t ldr, int ncols, double *Tout,
                                            Smem<NB, IB, WC> &sm) {
-  constexpr int NBLK = NB / IB;
-  constexpr int KOUT = (128 / IB) < NBLK ? (128 / IB) : NBLK;  // blocks per outer block
-  for (int b = 0; b < NBLK; b++) {
-    const int col0 = b * IB;
-    panel_block_at<NB, IB, WC, MODE>(b, Vt, ldv, vrows, R1, ldr, ncols, Tout, sm);
-    // ---- trailing update, two levels: block b is applied at once (from
-    //      LDS) only to the rest of its outer block of KOUT blocks; when an
-    //      outer block is complete, its KOUT blocks are applied together to
-    //      every column after it (V and T reloaded, double-buffered), so the
-    //      far columns see few, long MFMA passes instead of one per block.
-    {
-      const int oend = min(ncols, (b / KOUT + 1) * KOUT * IB);
-      for (int cs = col0 + IB; cs < oend; cs += CHUNK) {
-        const int nc = min(CHUNK, oend - cs);
-        apply_chunk<NB, IB, WC, MODE>(nullptr, 0, vrows, ncols, nullptr,
-                                      (MODE == M_UNM) ? nullptr : R1 + cs * ldr, ldr, Vt + cs * ldv,
-                                      ldv, vrows, nc, b, b + 1, true, false, sm);
-      }
-      if ((b % KOUT == KOUT - 1 || b == NBLK - 1) && oend < ncols) {
-        const int b0 = (b / KOUT) * KOUT;
-        __syncthreads();  // Vt, R1 and Tout written by every thread
-        for (int cs = oend; cs < ncols; cs += CHUNK) {
-          const int nc = min(CHUNK, ncols - cs);
-          apply_chunk<NB, IB, WC, MODE>(Vt, ldv, vrows, ncols, Tout,
-                                        (MODE == M_UNM) ? nullptr : R1 + cs * ldr, ldr, Vt + cs * ldv,
-                                        ldv, vrows, nc, b0, b + 1, false, false, sm);
-        }
-      }
-    }
-    __syncthreads();
-  }
+  for (int b = 0; b < NB / IB; b++) panel_block_at<NB, IB, WC, MODE>(b, Vt, ldv, vrows, R1, ldr, ncols, Tout, sm);
 }
 
 // ============================================================ solve kernels
@@ -1458,20 +1465,18 @@ __device__ __forceinline__ void run_task(const Problem &a, const Task &t, Smem<N
       }
       continue;
     }
-    // Whole-tile applies with the block loop unrolled (every block's row
-    // range, MFMAs and operand loads known at compile time): one 256 x 64
-    // chunk alone on a CU 1.2-1.3x faster than with the loop kept.
-    constexpr bool UNROLL = true;
+    // Whole-tile applies with the blocks fixed at compile time: one 256 x 64
+    // chunk alone on a CU 1.2-1.3x faster than with a runtime block loop.
     if (kind == K_UNMQR) {
-      apply_chunk<NB, IB, WC, M_UNM, UNROLL>(V, lda, vrows, vcols, Tof(t.i, t.k, 0), nullptr, 0, C2, ld,
+      apply_chunk<NB, IB, WC, M_UNM, 0, NB / IB>(V, lda, vrows, vcols, Tof(t.i, t.k, 0), nullptr, 0, C2, ld,
                                              vrows, nc, 0, NB / IB, false, dma, sm);
     } else {
       double *C1 = base + (int64_t)cs * ld + (int64_t)t.piv * NB;
       if (kind == K_TTMQR)
-        apply_chunk<NB, IB, WC, M_TT, UNROLL>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld, vrows,
+        apply_chunk<NB, IB, WC, M_TT, 0, NB / IB>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld, vrows,
                                               nc, 0, NB / IB, false, dma, sm);
       else
-        apply_chunk<NB, IB, WC, M_TS, UNROLL>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld, vrows,
+        apply_chunk<NB, IB, WC, M_TS, 0, NB / IB>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld, vrows,
                                               nc, 0, NB / IB, false, dma, sm);
     }
   }
