@@ -83,7 +83,7 @@ typedef struct tqr_opts {
   int32_t param;        /* PlasmaTree BS / GrASAP i (default 0)             */
   int32_t update_dtype; /* enum tqr_dtype (default TQR_F64)                 */
   int32_t exec;         /* enum tqr_exec (default persistent)               */
-  int32_t stripes;      /* update tasks per tile (0: 1 up to nb 128, 2 at 256) */
+  int32_t stripes;      /* update tasks per tile (0: 1 up to nb 128, 4 at 256) */
   int32_t max_refine;   /* refinement steps for mixed precision (def. 10)   */
   int32_t priority;     /* 1 = critical-path-first ready order (default 1)  */
   double refine_tol;    /* refinement stop, relative backward error (0=auto)*/

@@ -275,10 +275,10 @@ int resolve(const tqr_opts *o, Resolved *r, int64_t m = 0, int64_t n = 0) {
   r->refine_tol = x.refine_tol;
   const int wc = chunk_width(r->nb, r->ib);
   int s = x.stripes;
-  // default: one update task per tile up to nb = 128, two column stripes at
-  // nb = 256 (measured: per-task fixed costs outweigh the extra parallelism
-  // of narrower stripes)
-  if (s <= 0) s = (r->nb >= 256) ? 2 : 1;
+  // default: one update task per tile up to nb = 128, four 64-column
+  // stripes at nb = 256 (measured: 16384 x 2048 17.2 ms against 17.5 with
+  // two stripes and 18.6 with one; at nb 128 one task per tile is fastest)
+  if (s <= 0) s = (r->nb >= 256) ? 4 : 1;
   if (s > r->nb / wc) s = r->nb / wc;
   while ((r->nb / wc) % s) s--;  // stripe width is a multiple of the chunk width
   r->stripes = std::max(1, s);
