@@ -1144,7 +1144,11 @@ __device__ __forceinline__ void trsm_waves(const double *R, int64_t ldr, int nk,
     const int c1 = min(nk, c0 + CB);
     __syncthreads();  // the previous block's readers are done
     stage_cols<NB>(R + (int64_t)c0 * ldr, ldr, c1, c1 - c0, Ls);
-    if (tid < c1 - c0) rinv[tid] = 1.0 / R[(int64_t)(c0 + tid) * ldr + c0 + tid];
+    if (tid < c1 - c0) {  // the block's diagonal: reciprocals, and zero pivots reported
+      const double dd = R[(int64_t)(c0 + tid) * ldr + c0 + tid];
+      rinv[tid] = 1.0 / dd;
+      if (dd == 0.0) atomicMin(singular, row0 + c0 + tid + 1);
+    }
     __syncthreads();
     double uc[U], un[U];
     auto load_col = [&](int l, double *dst) {
@@ -1153,14 +1157,14 @@ __device__ __forceinline__ void trsm_waves(const double *R, int64_t ldr, int nk,
       for (int u = 0; u <= ub; u++) dst[u] = Ls[lc * NB + min(u * 64 + lane, c1 - 1)];
     };
     load_col(c1 - 1 - c0, uc);
+    double rc = rinv[c1 - 1 - c0];
     for (int l = c1 - 1 - c0; l >= 0; l--) {
-      const int r = c0 + l;
+      // the next step's column and reciprocal load while this step runs
       load_col(l - 1, un);
-      const double d = Ls[l * NB + r];
-      if (d == 0.0 && w == 0 && lane == 0) atomicMin(singular, row0 + r + 1);
+      const double rn = rinv[max(l - 1, 0)];
 #pragma unroll
       for (int c = 0; c < CPW; c++) {
-        const double xr = readlane_d(y[c][ub], l) * rinv[l];
+        const double xr = readlane_d(y[c][ub], l) * rc;
 #pragma unroll
         for (int u = 0; u <= ub; u++) {
           if (u < ub)
@@ -1171,6 +1175,7 @@ __device__ __forceinline__ void trsm_waves(const double *R, int64_t ldr, int nk,
       }
 #pragma unroll
       for (int u = 0; u <= ub; u++) uc[u] = un[u];
+      rc = rn;
     }
   }
 #pragma unroll
@@ -1321,13 +1326,14 @@ __device__ __forceinline__ void trsmt_waves(const double *R, int64_t ldr, int nk
         const int c1 = min(nk, c0 + CB);
         __syncthreads();
         stage_cols<NB>(R + (int64_t)c0 * ldr, ldr, c1, c1 - c0, Ls);
-        if (tid < c1 - c0) rinv[tid] = 1.0 / R[(int64_t)(c0 + tid) * ldr + c0 + tid];
+        if (tid < c1 - c0) {  // the block's diagonal: reciprocals, and zero pivots reported
+          const double dd = R[(int64_t)(c0 + tid) * ldr + c0 + tid];
+          rinv[tid] = 1.0 / dd;
+          if (dd == 0.0) atomicMin(singular, row0 + c0 + tid + 1);
+        }
         __syncthreads();
         for (int l = 0; l < c1 - c0; l++) {
-          const int r = c0 + l;
           const double *colr = Ls + l * NB;
-          const double d = colr[r];
-          if (d == 0.0 && w == 0 && lane == 0) atomicMin(singular, row0 + r + 1);
           double rv[U];
 #pragma unroll
           for (int u = 0; u <= ub; u++) rv[u] = colr[min(u * 64 + lane, c1 - 1)];
