@@ -1,37 +1,43 @@
 #!/usr/bin/env python3
 """Benchmark of the tiled QR path on one MI355X.
 
-Default workload (--workload tall): FP64 least squares on a tall-skinny
-matrix, m = 16384, n = 2048, tile nb = 256 (64 x 8 tiles), entries i.i.d.
-N(0,1) (seeded, synthetic), Greedy elimination tree, TT kernels.  One step
-is the whole hot path on one batch: tqr_lstsq, i.e. copy A and b into the
-workspace, then one persistent executor launch that factors A = QR, applies
-Q^T to b as the factorization proceeds, and back-substitutes
-R x = (Q^T b)(1:n) (elimination list and task graph are cached after the
-first call).  The same solve is then timed with FP32 and BF16 trailing
-updates plus FP64 refinement to the FP64 backward error, and with each of
-the five trees (FlatTree, BinaryTree, Fibonacci, Greedy, GrASAP) on the
-same input.
+Default workload (--workload square): least squares on square 8192 x 8192
+systems with prescribed condition number kappa in {1e2, 1e5, 1e8}:
+A = U diag(sigma) V^T with Haar U, V and sigma_i = kappa^(-(i-1)/(n-1)),
+b = A x + 1e-6 N(0,1) (seeded, synthetic).  Tile nb = 256 (32 x 32 tiles),
+ib = 32, Greedy elimination tree, TT kernels.  One step is the whole hot
+path on one system: tqr_lstsq, i.e. copy A and b into the workspace, then
+one persistent executor launch that factors A = QR, applies Q^T to b as the
+factorization proceeds and back-substitutes R x = (Q^T b)(1:n).  The value
+is the plain FP64 solve; the same systems are then solved with FP32 and
+BF16 trailing updates plus FP64 refinement to the FP64 backward error, per
+kappa, and their speed-ups over FP64 (and any cell that did not reach the
+FP64 error) are reported beside it.
+
+Also in the JSON line:
+  roofline    the dominant kernel (the executor launch) against the FP64
+              matrix peak: QR flops / mean launch duration (HIP events the
+              library records around each launch on the launch's stream);
+  gamma_ub    the thesis's upper-bound model gamma_task T / max(T/P, cp)
+              (section "Experimental results"), with the measured per-task
+              rates of one traced launch;
+  c2_trees    16384 x 2048 (64 x 8 tiles) FP64 least squares with the five
+              trees of the thesis on identical inputs;
+  cpu_baseline the FP64 oracle on a bounded column sample of the same matrix,
+              single-threaded and with all host cores.
 
 Other workloads (each prints its own JSON line):
-  --workload square   8192 x 8192 systems A = U diag(sigma) V^T with Haar U,
-                      V, log-spaced sigma, kappa in {1e2, 1e5, 1e8},
-                      b = A x + 1e-6 N(0,1); FP64, FP32 and BF16 updates.
+  --workload tall     16384 x 2048 least squares (the five trees, mixed
+                      precision, selector and a small tuning grid).
   --workload batched  512 ragged least-squares problems, m log-uniform in
                       [256, 8192], n log-uniform in [32, 512], n <= m/2,
                       N(0,1); FP32 updates + FP64 refinement, nb/ib from the
-                      autotuner, tree per problem by critical path; one
-                      executor launch per solve.
+                      autotuner, tree per problem by critical path.
 
 value = sum of 2 n^2 (m - n/3) over the problems / (seconds per step), in
 TFLOP/s: only the QR flops are counted although the step also applies Q^T
 and solves (and refines).  Inputs are resident in HBM when the timed region
 starts.
-
-The JSON line also carries the roofline of the dominant kernel (the
-executor launch, timed by HIP events that the library records around each
-launch on the launch's stream, inside the timed region) and the CPU oracle
-timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -64,16 +70,36 @@ def blas_threads():
         return 1
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def oracle_qr_rate(S, what):
     """The FP64 oracle (unblocked Householder, numpy) on the sample S, as a
-    rate in TFLOP/s of the same flop formula."""
+    rate in TFLOP/s of the same flop formula: once with every host core
+    available to its BLAS calls and once single-threaded."""
+    from threadpoolctl import threadpool_limits
     from oracle import householder as H
-    t0 = time.perf_counter()
-    H.qr(S)
-    dt = time.perf_counter() - t0
     m, n = S.shape
-    return {"value": qr_flops(m, n) / dt / 1e12, "unit": "TFLOP/s", "cores": int(blas_threads()),
-            "kind": "oracle", "seconds": dt, "sample": what}
+    runs = {}
+    for label, threads in (("all_cores", None), ("single_thread", 1)):
+        with threadpool_limits(limits=threads):
+            cores = int(blas_threads())
+            t0 = time.perf_counter()
+            H.qr(S)
+            dt = time.perf_counter() - t0
+        runs[label] = {"value": qr_flops(m, n) / dt / 1e12, "seconds": dt, "cores": cores}
+    out = {"value": runs["all_cores"]["value"], "unit": "TFLOP/s", "cores": runs["all_cores"]["cores"],
+           "kind": "oracle", "seconds": runs["all_cores"]["seconds"], "sample": what,
+           "single_thread": runs["single_thread"], "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    return out
 
 
 def timed(fn, steps, warmup, torch, T):
@@ -230,6 +256,93 @@ def run_tall(args, np, torch, T, synth):
     return out
 
 
+# ------------------------------------------------------- DAG upper bound
+def gamma_ub(T, torch, np, m, n, nrhs, opts, run_once, tree_name):
+    """The thesis's upper-bound model (section "Experimental results"):
+    gamma_ub = gamma_task T / max(T/P, cp), T the total work and cp the
+    critical path in units of nb^3/3 flop (table tab.kernels weights),
+    P the concurrent task slots (executor workgroups) and gamma_task the
+    per-workgroup kernel rate, here measured from one traced launch of the
+    same least-squares graph (factorization tasks' flops over their summed
+    durations).  A second form replaces the unit weights by every task's
+    measured duration: t_ub = max(W / P, longest measured path)."""
+    nb = opts.nb
+    p, q = -(-m // nb), -(-n // nb)
+    tasks = T.debug_graph(m, n, opts, nrhs=nrhs, kind=3)
+    off, succ = T.debug_succ(m, n, opts, nrhs=nrhs, kind=3)
+    nt = len(tasks)
+    buf = torch.zeros(4 * nt, dtype=torch.int64, device="cuda")
+    T.debug_trace(buf.data_ptr(), nt)
+    try:
+        run_once()
+        torch.cuda.synchronize()
+    finally:
+        T.debug_trace(None, 0)
+    tr = buf.cpu().numpy().reshape(nt, 4)
+    ticks_per_ms = float(T.wallclock_khz())
+    d = (tr[:, 1] - tr[:, 0]).astype(np.float64) / ticks_per_ms  # ms
+    kinds = np.array([t[0] for t in tasks])
+    P = T.executor_grid(opts)
+    unit = nb ** 3 / 3.0
+    weights = {0: 4, 1: 6, 2: 2, 3: 6, 4: 12, 5: 6}
+    # factorization tasks: the six kernels on A's own tile columns (j < q);
+    # the right-hand side's updates and the solve are excluded from the rate
+    fact = np.array([t[0] < 6 and t[4] < q for t in tasks])
+    units = 6 * p * q * q - 2 * q ** 3
+    cp_units = T.tqr_tree_cp(tree_name, p, q, 0, T.TT)
+    # a kernel split into column stripes is several tasks sharing its units
+    parts = {}
+    for t in tasks:
+        key = (t[0], t[1], t[2], t[3], t[4])
+        parts[key] = parts.get(key, 0) + 1
+    task_units = np.array([weights.get(t[0], 0) / parts[(t[0], t[1], t[2], t[3], t[4])] for t in tasks])
+    rate = task_units[fact].sum() * unit / d[fact].sum()  # flop per ms per workgroup
+    t_model = max(units / P, cp_units) * unit / rate
+    # measured-duration form: longest path through the graph (Kahn order)
+    indeg = np.zeros(nt, dtype=np.int64)
+    for e in succ:
+        indeg[e] += 1
+    ready = [t for t in range(nt) if indeg[t] == 0]
+    finish = np.zeros(nt)
+    while ready:
+        t = ready.pop()
+        finish[t] += d[t]
+        for e in range(off[t], off[t + 1]):
+            s_ = succ[e]
+            finish[s_] = max(finish[s_], finish[t])
+            indeg[s_] -= 1
+            if indeg[s_] == 0:
+                ready.append(s_)
+    cp_meas = float(finish.max())
+    W = float(d.sum())
+    t_meas = max(W / P, cp_meas)
+    flops = qr_flops(m, n)
+    span = (tr[:, 1].max() - tr[:, 0].min()) / ticks_per_ms
+    by_kind = {}
+    names = ["GEQRT", "TSQRT", "TTQRT", "UNMQR", "TSMQR", "TTMQR", "TRSM", "GEMM", "TRSMT", "GEMMT"]
+    for k in sorted(set(kinds.tolist())):
+        sel = kinds == k
+        by_kind[names[k]] = {"tasks": int(sel.sum()), "mean_us": float(d[sel].mean() * 1e3),
+                             "total_ms": float(d[sel].sum())}
+    return {"P": P, "T_units": units, "cp_units": cp_units,
+            "gamma_task_tflops_per_slot": rate / 1e9,
+            "thesis_model": {"t_ub_ms": t_model, "gamma_ub": flops / (t_model / 1e3) / 1e12,
+                             "bound": "T/P" if units / P >= cp_units else "cp"},
+            "measured_dag": {"t_ub_ms": t_meas, "gamma_ub": flops / (t_meas / 1e3) / 1e12,
+                             "work_over_P_ms": W / P, "critical_path_ms": cp_meas,
+                             "bound": "T/P" if W / P >= cp_meas else "cp"},
+            "traced_span_ms": float(span), "busy_fraction": W / (P * span), "per_kind": by_kind}
+
+
+def backward_error_square(np, A0, b0, x):
+    """Rigal-Gaches ||b - A x|| / (||A||_F ||x|| + ||b||), long double."""
+    Al = A0.astype(np.longdouble)
+    r = b0.astype(np.longdouble) - Al @ x.astype(np.longdouble)
+    nA = np.sqrt(np.sum(Al * Al))
+    xl, bl = x.astype(np.longdouble), b0.astype(np.longdouble)
+    return float(np.sqrt(np.dot(r, r)) / (nA * np.sqrt(np.dot(xl, xl)) + np.sqrt(np.dot(bl, bl))))
+
+
 # -------------------------------------------------------------------- square
 def run_square(args, np, torch, T, synth):
     n, nb = args.square_n, args.nb
@@ -237,7 +350,8 @@ def run_square(args, np, torch, T, synth):
     X = torch.empty((1, n), dtype=torch.float64, device=dev).t()
     info = torch.zeros(1, dtype=torch.int32, device=dev)
     per_kappa = {}
-    fp64_ms = fp64_kms = None
+    fp64 = None
+    gub = None
     for kappa in args.kappas:
         t0 = time.perf_counter()
         A0, x0, b0 = synth.conditioned(n, kappa, 7)
@@ -246,37 +360,85 @@ def run_square(args, np, torch, T, synth):
         b = T.colmajor(b0[:, None], dev)
         res = {}
         for dt in ["f64"] + list(args.mixed):
-            o = T.default_opts(nb=nb, ib=args.ib, tree=args.tree, update_dtype=dt, max_refine=20)
+            o = T.default_opts(nb=nb, ib=args.ib, tree=args.tree, update_dtype=dt, max_refine=args.max_refine)
             w = T.lstsq_workspace(n, n, 1, o, dev)
-            ms, kms, nl = timed(lambda: T.lstsq(A, b, o, X=X, work=w, info=info), args.steps, args.warmup, torch, T)
+            # the FP64 solve is kappa-independent: its full timing is taken once
+            steps = args.steps if (dt != "f64" or fp64 is None) else max(2, args.steps // 4)
+            ms, kms, nl = timed(lambda: T.lstsq(A, b, o, X=X, work=w, info=info), steps, args.warmup, torch, T)
             x = X[:, 0].cpu().numpy()
-            r = b0 - A0 @ x
-            be = float(np.linalg.norm(r) / (np.linalg.norm(A0) * np.linalg.norm(x) + np.linalg.norm(b0)))
+            be = backward_error_square(np, A0, b0, x)
             rep = T.refine_report(w)
-            res[dt] = {"ms_per_step": ms, "value": qr_flops(n, n) / (ms / 1e3) / 1e12,
-                       "refine_steps": rep["iterations"], "converged": rep["done"], "info": int(info.item()),
-                       "backward_error": be, "equal_fp64_error": bool(be <= 50 * EPS)}
-            if dt == "f64" and fp64_ms is None:
-                fp64_ms, fp64_kms = ms, kms
+            res[dt] = {"ms_per_step": ms, "value": qr_flops(n, n) / (ms / 1e3) / 1e12, "executor_ms": kms,
+                       "executor_launches_per_step": nl, "refine_steps": rep["iterations"],
+                       "converged": rep["done"], "info": int(info.item()), "backward_error": be,
+                       "equal_fp64_error": bool(be <= 50 * EPS and int(info.item()) == 0)}
+            if dt == "f64" and fp64 is None:
+                fp64 = {"ms": ms, "kms": kms, "be": be, "info": int(info.item())}
+                if not args.no_gamma_ub:
+                    gub = gamma_ub(T, torch, np, n, n, 1, o, lambda: T.lstsq(A, b, o, X=X, work=w, info=info),
+                                   args.tree)
             log("kappa %g %s: %.2f ms, be %.2e, refine %d, info %d" % (kappa, dt, ms, be, rep["iterations"],
                                                                      int(info.item())))
         for dt in args.mixed:
             res[dt]["speedup_vs_fp64"] = res["f64"]["ms_per_step"] / res[dt]["ms_per_step"]
         per_kappa["%g" % kappa] = res
         del A, b
-    out = base_line(args, qr_flops(n, n) / (fp64_ms / 1e3) / 1e12, fp64_ms, "f64",
-                    {"workload": "FP64 tiled-QR solve of square %dx%d systems with prescribed condition number "
-                                 "(Haar U, V; log-spaced sigma), nb=%d, %s tree" % (n, n, nb, args.tree),
-                     "n": n, "nb": nb, "ib": args.ib, "tree": args.tree, "kappas": args.kappas})
-    out["executor_ms"] = fp64_kms
+    if fp64["info"] != 0:
+        raise SystemExit("executor reported info=%d" % fp64["info"])
+    out = base_line(args, qr_flops(n, n) / (fp64["ms"] / 1e3) / 1e12, fp64["ms"], "f64",
+                    {"workload": "FP64 tiled-QR least squares of square %dx%d systems with prescribed condition "
+                                 "number (Haar U, V; log-spaced sigma; b = A x + 1e-6 N(0,1)), nb=%d (%dx%d tiles), "
+                                 "%s tree, TT kernels" % (n, n, nb, -(-n // nb), -(-n // nb), args.tree),
+                     "n": n, "nb": nb, "ib": args.ib, "tree": args.tree, "kappas": args.kappas,
+                     "precision": "plain FP64"})
+    out["executor_ms"] = fp64["kms"]
+    out["ls_backward_error"] = fp64["be"]
     out["per_kappa"] = per_kappa
-    out["roofline"] = roofline(qr_flops(n, n), fp64_kms, "exec_persistent (least-squares task graph)")
+    out["mixed_summary"] = {
+        dt: {k: {"speedup_vs_fp64": per_kappa[k][dt]["speedup_vs_fp64"],
+                 "equal_fp64_error": per_kappa[k][dt]["equal_fp64_error"]} for k in per_kappa}
+        for dt in args.mixed}
+    out["not_at_fp64_error"] = ["%s kappa=%s" % (dt, k) for k in per_kappa for dt in per_kappa[k]
+                                if not per_kappa[k][dt]["equal_fp64_error"]]
+    out["roofline"] = roofline(qr_flops(n, n), fp64["kms"],
+                               "exec_persistent (least-squares task graph: factor, Q^T b, R x = c)",
+                               recorded_traffic("traffic_lstsq_8192x8192_nb256.json",
+                                                "square %d nb=%d ib=%d %s lstsq" % (n, nb, args.ib, args.tree)))
+    if gub is not None:
+        out["gamma_ub"] = gub
+        out["roofline"]["gamma_ub"] = gub["measured_dag"]["gamma_ub"]
+        out["roofline"]["frac_of_gamma_ub"] = out["roofline"]["achieved"] / gub["measured_dag"]["gamma_ub"]
+    if not args.no_c2:
+        out["c2_trees"] = c2_trees(args, np, torch, T, synth)
     if not args.no_cpu_baseline:
         A0, _, _ = synth.conditioned(n, args.kappas[0], 7)
-        c = 64
+        c = args.cpu_sample_cols
+        log("cpu baseline: oracle on an %dx%d column sample" % (n, c))
         out["cpu_baseline"] = oracle_qr_rate(A0[:, :c].copy(order="F"),
                                              "unblocked FP64 Householder QR of the first %d columns of the "
-                                             "%dx%d kappa=%g matrix" % (c, n, n, args.kappas[0]))
+                                             "%dx%d kappa=%g matrix (%d x %d)" % (c, n, n, args.kappas[0], n, c))
+    return out
+
+
+def c2_trees(args, np, torch, T, synth, m=16384, n=2048, nb=256):
+    """FP64 least squares on 16384 x 2048 with the five trees on identical
+    inputs (time per solve and the tree's tiled critical path)."""
+    A0 = synth.gaussian(m, n, 1)
+    b0 = synth.gaussian_rhs(m, 1, 1)
+    dev = torch.device("cuda:0")
+    A = T.colmajor(A0, dev)
+    b = T.colmajor(b0, dev)
+    X = torch.empty((1, n), dtype=torch.float64, device=dev).t()
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = {"workload": "FP64 least squares, 16384x2048, nb=256 (64x8 tiles), N(0,1), seed 1"}
+    for tr in ["flat", "binary", "fibonacci", "greedy", "grasap"]:
+        ot = T.default_opts(nb=nb, ib=32, tree=tr)
+        wt = T.lstsq_workspace(m, n, 1, ot, dev)
+        tms, tkms, _ = timed(lambda: T.lstsq(A, b, ot, X=X, work=wt, info=info), 3, 1, torch, T)
+        cp = T.tqr_tree_cp(tr, -(-m // nb), -(-n // nb), 0, T.TT)
+        out[tr] = {"ms_per_step": tms, "value": qr_flops(m, n) / (tms / 1e3) / 1e12, "critical_path_units": cp,
+                   "info": int(info.item())}
+        log("c2 tree %s: %.2f ms (critical path %d units)" % (tr, tms, cp))
     return out
 
 
@@ -338,7 +500,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["tall", "square", "batched"], default="tall")
+    ap.add_argument("--workload", choices=["tall", "square", "batched"], default="square")
     ap.add_argument("--m", type=int, default=16384)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--square-n", type=int, default=8192)
@@ -352,6 +514,9 @@ def main():
     ap.add_argument("--kernels", default="tt")
     ap.add_argument("--stripes", type=int, default=0)
     ap.add_argument("--cpu-sample-cols", type=int, default=256)
+    ap.add_argument("--no-c2", action="store_true", help="skip the 16384x2048 five-tree comparison")
+    ap.add_argument("--no-gamma-ub", action="store_true", help="skip the traced launch of the DAG bound")
+    ap.add_argument("--max-refine", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed", nargs="*", default=["f32", "bf16"],
                     help="also time the solve with these update dtypes + FP64 refinement")

@@ -278,6 +278,12 @@ int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, in
 
 const char *tqr_strerror(int code);
 
+/* Number of workgroups of the persistent executor launch for the tile
+ * configuration of *o (NULL: defaults) on the current device: the number
+ * of tasks that can run at once (compute units x resident workgroups per
+ * unit).  Negative on unsupported options or a failed HIP query. */
+int tqr_executor_grid(const tqr_opts *o);
+
 /* ---------------------------------------------------------- diagnostics */
 
 /* Debug only, not thread-safe: while buf is non-NULL every executor launch
@@ -286,6 +292,20 @@ const char *tqr_strerror(int code);
  * and the hardware CU id that ran it.  buf is a device buffer owned by the
  * caller.  Pass NULL to stop. */
 void tqr_debug_trace(int64_t *buf, int64_t cap);
+
+/* Rate of the device wall clock used by the trace stamps and the watchdog
+ * (hipDeviceAttributeWallClockRate of the current device), in kHz, or a
+ * negative TQR_E_* code. */
+int64_t tqr_wallclock_khz(void);
+
+/* Debug only: the executor's watchdog limit, in device wall-clock ticks
+ * (hipDeviceAttributeWallClockRate kHz), for every later launch: a
+ * workgroup that waits longer than this for its queue slot to hold a ready
+ * task sets the abort flag, every workgroup then leaves the executor and
+ * info receives TQR_INFO_TIMEOUT (the results are then undefined).  0
+ * restores the default of 30 seconds.  A tiny limit forces the watchdog
+ * path from the host (failure-handling tests); every kernel still exits. */
+void tqr_debug_spin_limit(int64_t ticks);
 
 /* Diagnostics: with timing enabled, every executor launch is bracketed by a
  * pair of HIP events recorded on the launch's stream (the executor kernel

@@ -18,16 +18,32 @@ import math
 import numpy as np
 
 
+def _norm2(x):
+    """Euclidean norm without overflow or underflow in the squares: the
+    entries are divided by the largest magnitude first (so every square is
+    at most 1) and the result is scaled back."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.size == 0:
+        return 0.0
+    big = float(np.max(np.abs(x)))
+    if big == 0.0 or not math.isfinite(big):
+        return big
+    y = x / big
+    return big * math.sqrt(float(np.dot(y, y)))
+
+
 def reflector(x):
-    """(v, tau, beta) of the Householder reflector for the vector x."""
+    """(v, tau, beta) of the Householder reflector for the vector x.
+
+    ||x|| is formed with scaling (_norm2), so entries near the overflow or
+    underflow threshold give the same reflector as the scaled vector."""
     x = np.asarray(x, dtype=np.float64)
     alpha = float(x[0])
-    sigma = float(np.dot(x[1:], x[1:]))
     v = np.zeros_like(x)
     v[0] = 1.0
-    if sigma == 0.0:
+    if x.size == 1 or float(np.max(np.abs(x[1:]))) == 0.0:
         return v, 0.0, alpha
-    norm = math.sqrt(alpha * alpha + sigma)
+    norm = _norm2(x)
     beta = -norm if alpha >= 0.0 else norm
     tau = (beta - alpha) / beta
     v[1:] = x[1:] / (alpha - beta)
@@ -137,15 +153,29 @@ def orthogonality_error(Q):
     return np.linalg.norm(Q.T @ Q - np.eye(Q.shape[1]))
 
 
-def gram_error(A, R, probes=8, seed=0):
-    """Randomised check of R^T R = A^T A: max over Gaussian probes z of
-    ||R^T (R z) - A^T (A z)|| / (||A||_F^2 ||z||)."""
+def gram_probes(n, probes=8, seed=0):
+    """The Gaussian probe vectors gram_error uses (n x probes)."""
     rng = np.random.default_rng(seed)
-    nA = np.linalg.norm(A)
+    return np.stack([rng.standard_normal(n) for _ in range(probes)], axis=1)
+
+
+def gram_error(A, R, probes=8, seed=0):
+    """Randomised check of R^T R = A^T A: the largest relative error
+    ||R^T (R z) - A^T (A z)|| / ||A^T (A z)|| over Gaussian probes z.
+
+    The normalisation is the natural scale of the Gram action (about
+    ||A||_2^2 ||z||), so a backward-stable R gives a value of a few eps.
+    Both products are formed in extended precision (long double) so that
+    their own rounding does not mask an error of that size."""
+    Al = np.asarray(A, dtype=np.float64).astype(np.longdouble)
+    Rl = np.asarray(R, dtype=np.float64).astype(np.longdouble)
+    Z = gram_probes(Al.shape[1], probes, seed).astype(np.longdouble)
     worst = 0.0
-    for _ in range(probes):
-        z = rng.standard_normal(A.shape[1])
-        e = np.linalg.norm(R.T @ (R @ z) - A.T @ (A @ z)) / (nA * nA * np.linalg.norm(z))
+    for c in range(Z.shape[1]):
+        z = Z[:, c]
+        g = Al.T @ (Al @ z)
+        d = Rl.T @ (Rl @ z) - g
+        e = float(np.sqrt(np.dot(d, d)) / np.sqrt(np.dot(g, g)))
         worst = max(worst, e)
     return worst
 
@@ -156,17 +186,19 @@ def ls_backward_error(A, b, x):
     Square systems: Rigal-Gaches ||b - A x|| / (||A||_F ||x|| + ||b||).
     Rectangular: Stewart's one-sided bound ||A^T r|| / (||A||_F ||r||) with
     r = b - A x (x is the exact LS solution of a problem perturbed by
-    E = -r r^T A / ||r||^2, ||E||_2 = ||A^T r|| / ||r||).  The products are
-    formed in extended precision so that their own rounding does not mask
-    errors of order 50 eps."""
-    A = np.asarray(A, dtype=np.float64)
-    Al = A.astype(np.longdouble)
-    r = b.astype(np.longdouble) - Al @ x.astype(np.longdouble)
-    nA = float(np.linalg.norm(A))
-    if A.shape[0] == A.shape[1]:
-        return float(np.linalg.norm(r.astype(np.float64))) / (nA * np.linalg.norm(x) + np.linalg.norm(b))
-    atr = (Al.T @ r).astype(np.float64)
-    nr = float(np.linalg.norm(r.astype(np.float64)))
-    if nr == 0.0:
+    E = -r r^T A / ||r||^2, ||E||_2 = ||A^T r|| / ||r||).  Every product
+    and norm is formed in extended precision (long double, also wide enough
+    in exponent for entries near the FP64 overflow threshold) so that the
+    measure's own rounding does not mask errors of order 50 eps."""
+    Al = np.asarray(A, dtype=np.float64).astype(np.longdouble)
+    bl = np.asarray(b, dtype=np.float64).astype(np.longdouble)
+    xl = np.asarray(x, dtype=np.float64).astype(np.longdouble)
+    r = bl - Al @ xl
+    nA = np.sqrt(np.sum(Al * Al))
+    nr = np.sqrt(np.dot(r, r))
+    if Al.shape[0] == Al.shape[1]:
+        return float(nr / (nA * np.sqrt(np.dot(xl, xl)) + np.sqrt(np.dot(bl, bl))))
+    if nr == 0:
         return 0.0
-    return float(np.linalg.norm(atr)) / (nA * nr)
+    atr = Al.T @ r
+    return float(np.sqrt(np.dot(atr, atr)) / (nA * nr))

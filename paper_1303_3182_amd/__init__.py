@@ -9,7 +9,7 @@ Matrices are float64 column-major device tensors (stride (1, ld)).
 """
 from ._binding import (  # noqa: F401
     ASAP, BF16, BINARY, EXEC_PERSISTENT, EXEC_SEQUENTIAL, F32, F64, FIBONACCI, FLAT,
-    GRASAP, GREEDY, debug_graph, debug_succ, debug_timing, debug_timing_read, debug_trace, HYBRID, PLASMA, TREES, TT, AUTO, Opts, TqrError, default_opts, lib,
+    GRASAP, GREEDY, debug_graph, debug_spin_limit, debug_succ, debug_timing, debug_timing_read, debug_trace, executor_grid, wallclock_khz, HYBRID, PLASMA, TREES, TT, AUTO, Opts, TqrError, default_opts, lib,
     library_path, tqr_apply_qt, tqr_factor, tqr_factor_ex, tqr_graph_stats, tqr_lstsq,
     tqr_lstsq_work_size, tqr_solve_r, tqr_tree_cp, tqr_tree_list, tqr_workspace_size,
 )

@@ -74,6 +74,9 @@ def lib():
             "tqr_set_selector": (ctypes.c_int, [vp]),
             "tqr_select": (ctypes.c_int, [i64, i64, i32, i32p, i32p, i32p]),
             "tqr_debug_trace": (None, [vp, i64]),
+            "tqr_debug_spin_limit": (None, [i64]),
+            "tqr_executor_grid": (ctypes.c_int, [op]),
+            "tqr_wallclock_khz": (i64, []),
             "tqr_debug_timing": (None, [i32]),
             "tqr_debug_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), i64p]),
             "tqr_debug_graph": (ctypes.c_int, [i64, i64, i64, i32, op, i32p, i64]),
@@ -201,6 +204,28 @@ def debug_timing_read():
 def debug_trace(buf_ptr, cap):
     """Record per-task clock stamps into a device int64 buffer (debug)."""
     lib().tqr_debug_trace(buf_ptr, cap)
+
+
+def executor_grid(opts=None):
+    """Workgroups of the persistent executor launch (concurrent task slots)."""
+    g = lib().tqr_executor_grid(_opts_ptr(opts))
+    if g < 0:
+        _check(g, "tqr_executor_grid")
+    return g
+
+
+def wallclock_khz():
+    """Rate of the device wall clock of the trace stamps, in kHz."""
+    k = lib().tqr_wallclock_khz()
+    if k <= 0:
+        _check(int(k), "tqr_wallclock_khz")
+    return int(k)
+
+
+def debug_spin_limit(ticks):
+    """Watchdog limit of later executor launches in wall-clock ticks (0 =
+    the default of 30 s); debug and failure-handling tests only."""
+    lib().tqr_debug_spin_limit(int(ticks))
 
 
 def debug_graph(m, n, opts=None, nrhs=0, kind=0):

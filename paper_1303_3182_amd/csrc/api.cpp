@@ -152,8 +152,11 @@ int grid_size(int dev, int nb, int ib) {
   return grid;
 }
 
+int64_t g_spin_override = 0;  // tqr_debug_spin_limit; 0 = the default below
+
 int64_t spin_limit_ticks(int dev) {
   std::lock_guard<std::mutex> lk(g_mu);
+  if (g_spin_override > 0) return g_spin_override;
   auto it = g_spin.find({dev, 0});
   if (it != g_spin.end()) return it->second;
   int khz = 0;
@@ -1009,7 +1012,11 @@ int tqr_lstsq_batched(int32_t count, const int64_t *m, const int64_t *n, int64_t
       R.S = sw;
       R.lds = n[x];
       R.partial = w + L.part[x];
-      R.square = 0;  // batched refinement: semi-normal equations for every problem
+      // the correction always comes from the semi-normal equations (S);
+      // the stopping test of a square member is Rigal-Gaches, whose
+      // residual reaches rounding level (Stewart's bound would stay near
+      // 1/kappa for a consistent system)
+      R.square = (m[x] == n[x]) ? 1 : 0;
     }
     rf[x] = R;
   }
@@ -1287,6 +1294,28 @@ int tqr_debug_timing_read(double *ms_total, int64_t *launches) {
   if (ms_total) *ms_total = tot;
   if (launches) *launches = (int64_t)g_events.size();
   return TQR_OK;
+}
+
+int tqr_executor_grid(const tqr_opts *o) {
+  Resolved r;
+  const int rc = resolve(o, &r);
+  if (rc) return rc;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TQR_E_HIP;
+  return grid_size(dev, r.nb, r.ib);
+}
+
+int64_t tqr_wallclock_khz(void) {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TQR_E_HIP;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return TQR_E_HIP;
+  return khz;
+}
+
+void tqr_debug_spin_limit(int64_t ticks) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_spin_override = ticks > 0 ? ticks : 0;
 }
 
 void tqr_debug_trace(int64_t *buf, int64_t cap) {

@@ -115,6 +115,15 @@ __device__ __forceinline__ double group_sum(double v) {
   if (G == 16) v += dpp_d<0x140>(v);  // row_mirror: lane i <-> 15 - i
   return v;
 }
+template <int G>
+__device__ __forceinline__ double group_max(double v) {
+  static_assert(G == 8 || G == 16, "group of 8 or 16 lanes");
+  v = fmax(v, dpp_d<0xB1>(v));
+  v = fmax(v, dpp_d<0x4E>(v));
+  v = fmax(v, dpp_d<0x141>(v));
+  if (G == 16) v = fmax(v, dpp_d<0x140>(v));
+  return v;
+}
 
 // --------------------------------------------------------------- smem
 template <int NB, int IB, int WC>
@@ -756,11 +765,44 @@ __device__ __forceinline__ void panel_block(double *Vt, int64_t ldv, int vrows, 
       if (jt == j) {
         const double sig = sig_n, alpha = alpha_n;
         double tau = 0.0, beta = alpha, scale = 0.0;
-        if (sig != 0.0) {
-          const double nrm = hsqrt(fma(alpha, alpha, sig));
+        const double s2 = fma(alpha, alpha, sig);
+        if (sig >= 0x1p-960 && s2 <= 0x1p960) {
+          const double nrm = hsqrt(s2);
           beta = (alpha >= 0.0) ? -nrm : nrm;
           tau = (beta - alpha) * hrcp(beta);
           scale = hrcp(alpha - beta);
+        } else {
+          // The unscaled squares under- or overflow (or the column below
+          // the diagonal is zero): ||x|| from the column scaled by a power
+          // of two near its largest magnitude.  tau = 0 only when every
+          // entry below the diagonal is exactly zero.
+          double mx = 0.0;
+#pragma unroll
+          for (int u = 0; u < UH; u++) mx = fmax(mx, zmask(fabs(x[u]), head_role(g + RG * u, j) == 2));
+#pragma unroll
+          for (int u = UH; u < PRU; u++) mx = fmax(mx, fabs(x[u]));
+          mx = group_max<RG>(mx);
+          if (mx > 0.0) {
+            int e;
+            frexp(fmax(mx, fabs(alpha)), &e);
+            double ss = 0.0;
+#pragma unroll
+            for (int u = 0; u < UH; u++) {
+              const double y = ldexp(x[u], -e);
+              ss += zmask(y * y, head_role(g + RG * u, j) == 2);
+            }
+#pragma unroll
+            for (int u = UH; u < PRU; u++) {
+              const double y = ldexp(x[u], -e);
+              ss = fma(y, y, ss);
+            }
+            ss = group_sum<RG>(ss);
+            const double a = ldexp(alpha, -e);
+            const double nrm = ldexp(hsqrt(fma(a, a, ss)), e);
+            beta = (alpha >= 0.0) ? -nrm : nrm;
+            tau = (beta - alpha) * hrcp(beta);
+            scale = hrcp(alpha - beta);
+          }
         }
 #pragma unroll
         for (int u = 0; u < UH; u++) {

@@ -18,9 +18,12 @@ constexpr int kFroBlocks = 256;  // partial sums of ||A||_F^2
 typedef tqr_refine_report RefineState;
 
 // One problem of a refinement: the caller's A and B, the iterate X (n x
-// nrhs), the residual R (m x nrhs; for square problems also the correction,
-// in place), A^T R and then the correction S (n x nrhs, rectangular only),
-// scratch of refine_partial_bytes, the state and an optional info word.
+// nrhs), the residual R (m x nrhs), A^T R and then the correction S (n x
+// nrhs; null for classical refinement, whose correction overwrites R in
+// place), scratch of refine_partial_bytes, the state and an optional info
+// word.  `square` selects the stopping measure (Rigal-Gaches for square
+// systems, Stewart's bound otherwise), independently of where the
+// correction comes from.
 struct RefProb {
   const double *A;
   int64_t lda, m, n;

@@ -184,6 +184,9 @@ __global__ __launch_bounds__(RT) void check(const RefProb *tab, RefProb one, dou
       const double sn = sqrt(block_sum(ss, red));
       be = (rn == 0.0) ? 0.0 : sn / (anorm * rn);
     }
+    // a NaN or infinite measure (overflow in the low-precision updates, a
+    // non-finite input) is a failure, never a pass: fmax would drop a NaN
+    if (!(be <= 1.7976931348623157e308)) be = INFINITY;
     worst = fmax(worst, be);
   }
   if (threadIdx.x == 0) {
@@ -194,14 +197,15 @@ __global__ __launch_bounds__(RT) void check(const RefProb *tab, RefProb one, dou
   }
 }
 
-// X += D (D = S for rectangular problems, the first n rows of R for square ones)
+// X += D: D = S when the correction came from the semi-normal equations
+// (S given), else the first n rows of R (classical refinement, in place).
 __global__ __launch_bounds__(RT) void update(const RefProb *tab, RefProb one) {
   const RefProb &P = pick(tab, one);
   if (P.st->done) return;
   const int64_t k = (int64_t)blockIdx.x * RT + threadIdx.x;
   if (k >= P.n * P.nrhs) return;
   const int64_t z = k / P.n, i = k % P.n;
-  const double d = P.square ? P.R[z * P.ldr + i] : P.S[z * P.lds + i];
+  const double d = P.S ? P.S[z * P.lds + i] : P.R[z * P.ldr + i];
   P.X[z * P.ldx + i] += d;
 }
 

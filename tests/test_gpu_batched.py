@@ -86,3 +86,26 @@ def test_autotuner_picks_a_built_config_and_caches():
     Xs = T.lstsq_batched(dA, dB, o)
     torch.cuda.synchronize()
     _check(shapes, As, Bs, Xs, "autotuned")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_batched_square_member_converges(dtype):
+    """A square member of a low-precision batch is stopped by the
+    Rigal-Gaches measure (its residual reaches rounding level), so it
+    converges like the rectangular members instead of running out of
+    refinement steps."""
+    shapes = [(300, 100), (200, 200), (500, 60)]
+    As = [synth.gaussian(m, n, 70 + i) for i, (m, n) in enumerate(shapes)]
+    Bs = [synth.gaussian_rhs(m, 1, 70 + i) for i, (m, n) in enumerate(shapes)]
+    case("batched square member %s" % dtype)
+    o = T.default_opts(nb=64, ib=16, tree="greedy", update_dtype=dtype, max_refine=20)
+    dA = [T.colmajor(a) for a in As]
+    dB = [T.colmajor(b) for b in Bs]
+    work = T.lstsq_batched_workspace(shapes, 1, o)
+    info = torch.full((len(shapes),), -7, dtype=torch.int32, device="cuda")
+    Xs = T.lstsq_batched(dA, dB, o, work=work, info=info)
+    torch.cuda.synchronize()
+    reps = T.refine_reports(work, len(shapes))
+    assert info.cpu().tolist() == [0] * len(shapes), reps
+    assert all(r["done"] == 1 for r in reps), reps
+    _check(shapes, As, Bs, Xs, ("square member", dtype))

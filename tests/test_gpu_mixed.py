@@ -97,3 +97,17 @@ def test_fp64_lstsq_report_untouched_by_refinement():
     B0 = synth.gaussian_rhs(300, 1, 1)
     X, info, rep = _lstsq(A0, B0, T.default_opts(nb=64))
     assert info == 0 and rep["done"] == 0 and rep["iterations"] == 0 and rep["history"] == []
+
+
+def test_overflow_in_low_precision_updates_is_not_reported_as_success():
+    """Entries near 2^126: the FP32 updates overflow and the factorization
+    holds Inf / NaN.  The refinement must not call a NaN backward error a
+    pass: the report stays not-done and info is TQR_INFO_NOCONV."""
+    case("f32 overflow")
+    A0 = synth.gaussian(600, 200, 8) * 2.0 ** 126
+    B0 = synth.gaussian_rhs(600, 1, 8) * 2.0 ** 126
+    o = T.default_opts(nb=64, tree="greedy", update_dtype="f32", max_refine=3)
+    X, info, rep = _lstsq(A0, B0, o)
+    assert rep["done"] == 0, rep
+    assert info == -1001, info  # TQR_INFO_NOCONV
+    assert not (rep["backward_error"] <= 16 * EPS), rep

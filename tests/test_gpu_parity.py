@@ -6,7 +6,7 @@ import torch
 import paper_1303_3182_amd as T
 import synth
 from oracle import householder as H
-from tests.gpu_util import EPS, case, r_tol
+from tests.gpu_util import EPS, case, r_tol, trace_violations
 
 pytestmark = pytest.mark.gpu
 
@@ -193,3 +193,88 @@ def test_tall_skinny_full_size_five_trees():
         diags.append(np.abs(np.diag(R)))
     for dg in diags[1:]:
         assert np.max(np.abs(dg - diags[0]) / diags[0]) <= 1e-10
+
+
+@pytest.mark.parametrize("kernels", ["tt", "hybrid"])
+def test_executor_trace_respects_dependencies(kernels):
+    """Post-hoc check of a normal run: with per-task clock stamps on, every
+    task of the least-squares graph ran, and no task started before any of
+    its predecessors had ended (the executor's data-flow contract)."""
+    for (m, n, nb, ib) in [(1000, 333, 64, 16), (2048, 768, 256, 32)]:
+        case("trace %s m=%d n=%d nb=%d" % (kernels, m, n, nb))
+        o = T.default_opts(nb=nb, ib=ib, tree="greedy", kernels=kernels)
+        nt = len(T.debug_graph(m, n, o, nrhs=1, kind=3))
+        off, succ = T.debug_succ(m, n, o, nrhs=1, kind=3)
+        buf = torch.zeros(4 * nt, dtype=torch.int64, device="cuda")
+        A0 = synth.gaussian(m, n, 3)
+        b0 = synth.gaussian_rhs(m, 1, 3)
+        T.debug_trace(buf.data_ptr(), nt)
+        try:
+            X = T.lstsq(T.colmajor(A0), T.colmajor(b0), o)
+            torch.cuda.synchronize()
+        finally:
+            T.debug_trace(None, 0)
+        assert trace_violations(off, succ, buf.cpu().numpy(), nt) == []
+        assert H.ls_backward_error(A0, b0[:, 0], X.cpu().numpy()[:, 0]) <= 50 * EPS
+
+
+def test_watchdog_fires_and_the_executor_drains():
+    """Failure handling forced from the host: with a watchdog limit of one
+    clock tick, a workgroup that finds its queue slot not yet filled aborts
+    the launch; every workgroup then leaves, info reports the timeout, and
+    the next launch (default limit) is correct again."""
+    case("watchdog")
+    A0 = synth.gaussian(512, 256, 4)
+    o = T.default_opts(nb=128, tree="greedy")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    T.debug_spin_limit(1)
+    try:
+        T.factor(T.colmajor(A0), o, info=info)
+        torch.cuda.synchronize()
+    finally:
+        T.debug_spin_limit(0)
+    assert int(info.item()) == -1000  # TQR_INFO_TIMEOUT
+    A, W = _factor(A0, o)
+    _check_factorization(A0, A, W, o, "after watchdog")
+
+
+@pytest.mark.parametrize("s", [530, -530])
+@pytest.mark.parametrize("kernels", ["tt", "hybrid"])
+def test_extreme_scaling(s, kernels):
+    """Entries near the FP64 overflow (2^530 ~ 1e160) or underflow (2^-530)
+    threshold, where the unscaled squares of a Householder norm over- or
+    underflow: R equals 2^s times the oracle's R of the unscaled matrix (to
+    the FP64 bar) and the least-squares solution meets 50 eps."""
+    for (m, n, nb) in [(700, 300, 64), (1024, 512, 256)]:
+        case("scaling 2^%d %s m=%d n=%d nb=%d" % (s, kernels, m, n, nb))
+        A0 = synth.gaussian(m, n, 40 + m)
+        b0 = synth.gaussian_rhs(m, 1, 40 + m)
+        As, bs = A0 * 2.0 ** s, b0 * 2.0 ** s
+        o = T.default_opts(nb=nb, tree="greedy", kernels=kernels)
+        A, W = _factor(As, o)
+        R = np.triu(A.cpu().numpy()[:n, :n]) * 2.0 ** -s
+        Ro, _, _ = H.qr(A0)
+        Ra, _ = H.row_sign_align(R, Ro)
+        assert np.all(np.isfinite(R))
+        assert np.linalg.norm(Ra - Ro) <= r_tol(A0)
+        X = T.lstsq(T.colmajor(As), T.colmajor(bs), o)
+        torch.cuda.synchronize()
+        assert H.ls_backward_error(As, bs[:, 0], X.cpu().numpy()[:, 0]) <= 50 * EPS
+
+
+def test_tiny_subdiagonal_is_still_reduced():
+    """A column whose entries below the diagonal are far below the
+    underflow threshold of their squares (1e-170 under a unit diagonal)
+    still gets a reflector that zeroes them (tau = 0 only for an exactly
+    zero column), as in the oracle."""
+    case("tiny subdiagonal")
+    A0 = np.asfortranarray(np.vstack([np.eye(64), 1e-170 * synth.gaussian(64, 64, 5)]))
+    o = T.default_opts(nb=64, ib=16, tree="greedy")
+    A, W = _factor(A0, o)
+    R = np.triu(A.cpu().numpy()[:64, :64])
+    Ro, _, _ = H.qr(A0)
+    assert np.array_equal(np.sign(np.diag(R)), np.sign(np.diag(Ro)))
+    Bm = T.colmajor(A0)
+    T.apply_qt(A, W, Bm, o)
+    torch.cuda.synchronize()
+    assert np.abs(Bm.cpu().numpy()[64:]).max() <= 1e-10 * 1e-170

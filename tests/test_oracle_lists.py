@@ -244,3 +244,58 @@ def test_appendix_lists_small():
     assert sorted(g, key=lambda e: (e[2], g.index(e))) == [(4, 2, 1), (3, 1, 1), (2, 1, 1), (4, 3, 2), (3, 2, 2)]
     _, crs = T.coarse(4, 2, g)
     assert (crs[3, 0], crs[2, 0], crs[1, 0], crs[3, 1], crs[2, 1]) == (1, 1, 2, 2, 3)
+
+
+# Hybrid (TS) mode, derived by hand from the four dependency rules of
+# algorithm alg.elimSQ (GEQRT(piv) < TSQRT; GEQRT(piv) < UNMQR(piv, j);
+# UNMQR(piv, j) < TSMQR(j); TSQRT < TSMQR(j)), the data flow between
+# successive eliminations that share a tile (each kernel that rewrites a
+# tile waits for the previous writer), the rule that an already triangular
+# tile is not factored again, and the weights of table tab.kernels
+# (GEQRT 4, TSQRT 6, TTQRT 2, UNMQR 6, TSMQR 12, TTMQR 6).  Intervals are
+# [start, end]; "zero" is the end of the kernel that zeroes the tile.
+HYBRID_BY_HAND = {
+    # FlatTree 2x2, list [(2,1,1)]:
+    #   GEQRT(1,1) [0,4]; UNMQR(1,1,2) [4,10]; TSQRT(2,1,1) [4,10];
+    #   TSMQR(2,1,1,2) after UNMQR and TSQRT [10,22] (the 22 of the text);
+    #   the last diagonal tile is factored: GEQRT(2,2) [22,26].
+    ("flat", 2, 2): (26, {(2, 1): 10}, (2, 1, 0, 1, 1, 0)),
+    # FlatTree 3x2, list [(2,1,1),(3,1,1),(3,2,2)]:
+    #   GEQRT(1,1) [0,4]; UNMQR(1,1,2) [4,10]; TSQRT(2,1,1) [4,10];
+    #   TSMQR(2,1,1,2) [10,22]; TSQRT(3,1,1) after TSQRT(2,1,1) (both
+    #   rewrite R(1,1)) [10,16]; TSMQR(3,1,1,2) after TSMQR(2,1,1,2) (both
+    #   rewrite tile (1,2)) [22,34]; GEQRT(2,2) after TSMQR(2,1,1,2)
+    #   [22,26]; TSQRT(3,2,2) needs tile (3,2) from TSMQR(3,1,1,2) [34,40].
+    ("flat", 3, 2): (40, {(2, 1): 10, (3, 1): 16, (3, 2): 40}, (2, 3, 0, 1, 2, 0)),
+    # FlatTree 4x2: as 3x2 plus TSQRT(4,1,1) [16,22], TSMQR(4,1,1,2)
+    #   after TSMQR(3,1,1,2) [34,46]; TSQRT(4,2,2) (pivot 2 already
+    #   triangular) after TSQRT(3,2,2) and TSMQR(4,1,1,2) [46,52].
+    ("flat", 4, 2): (52, {(2, 1): 10, (3, 1): 16, (4, 1): 22, (3, 2): 40, (4, 2): 52}, (2, 5, 0, 1, 3, 0)),
+    # FlatTree 3x3: column 1 as 3x2 with the same kernels on tile column 3
+    #   (UNMQR(1,1,3) [4,10], TSMQR(2,1,1,3) [10,22], TSMQR(3,1,1,3)
+    #   [22,34]); GEQRT(2,2) [22,26]; UNMQR(2,2,3) after GEQRT(2,2) and
+    #   TSMQR(2,1,1,3) [26,32]; TSQRT(3,2,2) [34,40]; TSMQR(3,2,2,3) after
+    #   TSQRT(3,2,2), UNMQR(2,2,3) and TSMQR(3,1,1,3) [40,52]; the last
+    #   diagonal tile: GEQRT(3,3) [52,56].
+    ("flat", 3, 3): (56, {(2, 1): 10, (3, 1): 16, (3, 2): 40}, (3, 3, 0, 3, 5, 0)),
+    # Greedy 4x2, list [(4,2,1),(3,1,1),(2,1,1),(4,3,2),(3,2,2)]:
+    #   GEQRT(2,1) [0,4], UNMQR(2,1,2) [4,10], TSQRT(4,2,1) [4,10],
+    #   TSMQR(4,2,1,2) [10,22]; GEQRT(1,1) [0,4], UNMQR(1,1,2) [4,10],
+    #   TSQRT(3,1,1) [4,10], TSMQR(3,1,1,2) [10,22]; tile (2,1) is a
+    #   triangle: TTQRT(2,1,1) after both TSQRTs [10,12], TTMQR(2,1,1,2)
+    #   after both TSMQRs [22,28]; GEQRT(3,2) after TSMQR(3,1,1,2) [22,26],
+    #   TSQRT(4,3,2) after it [26,32]; GEQRT(2,2) after TTMQR [28,32],
+    #   TTQRT(3,2,2) after GEQRT(2,2) and TSQRT(4,3,2) [32,34].
+    ("greedy", 4, 2): (34, {(4, 1): 10, (3, 1): 10, (2, 1): 12, (4, 2): 32, (3, 2): 34}, (4, 3, 2, 2, 2, 1)),
+}
+
+
+@pytest.mark.parametrize("key", list(HYBRID_BY_HAND))
+def test_hybrid_times_derived_by_hand(key):
+    tree, p, q = key
+    cp, zeros, counts = HYBRID_BY_HAND[key]
+    res = T.tiled(p, q, T.elimination_list(tree, p, q), T.HYBRID)
+    assert res["cp"] == cp
+    for (i, k), t in zeros.items():
+        assert res["zero"][i - 1, k - 1] == t, (i, k)
+    assert tuple(res["counts"][n] for n in T.KERNELS) == counts
