@@ -276,6 +276,23 @@ int64_t tqr_tree_cp(int32_t tree, int32_t p, int32_t q, int32_t param, int32_t k
  * given problem (factor only).  No GPU is touched. */
 int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, int64_t *nedges);
 
+/* Bounded-processor schedule analysis of the factorization's task graph
+ * for the problem and options given (the graph tqr_factor runs: tree,
+ * kernel family, update stripes; weights of table tab.kernels divided
+ * among a tile's stripes), on P processors, from the thesis's chapters
+ * "Scheduling of Cholesky Factorization" (section "ALAP Derived Performance
+ * Bound", equation eqn:alapbound) and "Scheduling of QR Factorization"
+ * (section "Optimality", table tab:5x5_optimal).  out[5] receives, in units
+ * of nb^3/3: the critical path; the total work T_seq; the lost area LA_P
+ * of P processors at the end of the as-late-as-possible execution on
+ * unbounded processors; the ALAP derived bound max(cp, (T_seq + LA_P)/P),
+ * a lower bound on any schedule's length on P processors; and the length of
+ * the critical-path list schedule on P processors (an idle processor takes
+ * the ready task of largest bottom level; ties to the task ready first,
+ * then to the later one in list order).  Host only: no GPU is touched.
+ * Returns 0, or -i for an illegal i-th argument. */
+int tqr_schedule_bounds(int64_t m, int64_t n, const tqr_opts *o, int32_t P, double *out);
+
 const char *tqr_strerror(int code);
 
 /* Number of workgroups of the persistent executor launch for the tile

@@ -57,6 +57,7 @@ def lib():
             "tqr_tree_list": (i64, [i32, i32, i32, i32, i32p, i32p, i32p, i64]),
             "tqr_tree_cp": (i64, [i32, i32, i32, i32, i32, i64p, i64p]),
             "tqr_graph_stats": (ctypes.c_int, [i64, i64, op, i64p, i64p]),
+            "tqr_schedule_bounds": (ctypes.c_int, [i64, i64, op, i32, ctypes.POINTER(ctypes.c_double)]),
             "tqr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "tqr_lstsq_batched_work_size": (sz, [i32, i64p, i64p, i64, op]),
             "tqr_lstsq_batched": (ctypes.c_int, [i32, i64p, i64p, i64, vpp, i64p, vpp, i64p, vpp, i64p, vp, sz, op,
@@ -185,6 +186,15 @@ def tqr_graph_stats(m, n, opts=None):
     _check(lib().tqr_graph_stats(m, n, _opts_ptr(opts), ctypes.byref(nt), ctypes.byref(ne)),
            "tqr_graph_stats")
     return nt.value, ne.value
+
+
+def tqr_schedule_bounds(m, n, opts=None, P=1):
+    """Bounded-processor analysis of the factorization graph on P
+    processors: dict of cp, t_seq, lost_area, alap_bound and list_makespan
+    (units nb^3/3)."""
+    out = (ctypes.c_double * 5)()
+    _check(lib().tqr_schedule_bounds(m, n, _opts_ptr(opts), P, out), "tqr_schedule_bounds")
+    return dict(zip(("cp", "t_seq", "lost_area", "alap_bound", "list_makespan"), list(out)))
 
 
 def debug_timing(enable):

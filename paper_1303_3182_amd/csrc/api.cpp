@@ -1272,6 +1272,34 @@ int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, in
   return hp->valid ? TQR_OK : TQR_E_INTERNAL;
 }
 
+int tqr_schedule_bounds(int64_t m, int64_t n, const tqr_opts *o, int32_t P, double *out) {
+  if (m < 1) return -1;
+  if (n < 1 || n > m) return -2;
+  if (P < 1) return -4;
+  if (!out) return -5;
+  Resolved r;
+  int rc = resolve(o, &r, m, n);
+  if (rc) return rc;
+  // a fresh graph: the cached plans drop their predecessor lists
+  const PlanKey k = make_key(PK_FACTOR, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), 0, r);
+  GraphSpec spec;
+  spec.p = k.p;
+  spec.q = k.q;
+  spec.family = k.family;
+  spec.stripes = k.stripes;
+  Graph g = build_graph(make_list(k.tree, k.p, k.q, k.param), spec);
+  finalize(g, true);
+  if (!validate(g)) return TQR_E_INTERNAL;
+  double tseq = 0.0;
+  for (double w : g.weight) tseq += w;
+  out[0] = g.cp;
+  out[1] = tseq;
+  out[2] = alap_lost_area(g, P);
+  out[3] = alap_bound(g, P);
+  out[4] = list_makespan(g, P);
+  return TQR_OK;
+}
+
 void tqr_debug_timing(int32_t enable) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto &pr : g_events) {

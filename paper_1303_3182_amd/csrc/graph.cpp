@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cstdlib>
 #include <functional>
+#include <queue>
+#include <utility>
 
 namespace tqr {
 
@@ -422,6 +424,93 @@ void finalize(Graph &g, bool priority) {
                      [&](int32_t a, int32_t b) { return g.bottom[a] > g.bottom[b]; });
   g.order.resize(n);
   for (int t = 0; t < n; t++) g.order[t] = t;
+}
+
+// ------------------------------------------------- bounded processors
+double alap_lost_area(const Graph &g, int P) {
+  const int n = (int)g.tasks.size();
+  if (n == 0 || P < 1) return 0.0;
+  double cp = 0.0;
+  for (int t = 0; t < n; t++) cp = std::max(cp, g.bottom[t]);
+  // +1 at an ALAP start, -1 at its end; the busy count is constant between
+  // consecutive event times.
+  std::vector<std::pair<double, int>> ev;
+  ev.reserve(2 * (size_t)n);
+  for (int t = 0; t < n; t++) {
+    const double st = cp - g.bottom[t];
+    ev.emplace_back(st, +1);
+    ev.emplace_back(st + g.weight[t], -1);
+  }
+  std::sort(ev.begin(), ev.end());
+  // busy[x] holds on [time[x], time[x+1])
+  std::vector<double> time;
+  std::vector<int> busy;
+  int cur = 0;
+  for (size_t e = 0; e < ev.size();) {
+    const double x = ev[e].first;
+    while (e < ev.size() && ev[e].first == x) cur += ev[e++].second;
+    time.push_back(x);
+    busy.push_back(cur);
+  }
+  double la = 0.0;
+  for (int x = (int)time.size() - 2; x >= 0; x--) {
+    if (busy[x] > P) break;
+    la += (double)(P - busy[x]) * (time[x + 1] - time[x]);
+  }
+  return la;
+}
+
+double alap_bound(const Graph &g, int P) {
+  double cp = 0.0, tseq = 0.0;
+  for (size_t t = 0; t < g.tasks.size(); t++) {
+    cp = std::max(cp, g.bottom[t]);
+    tseq += g.weight[t];
+  }
+  return std::max(cp, (tseq + alap_lost_area(g, P)) / P);
+}
+
+double list_makespan(const Graph &g, int P) {
+  const int n = (int)g.tasks.size();
+  if (n == 0 || P < 1) return 0.0;
+  struct Ready {
+    double pri, at;
+    int32_t id;
+    bool operator<(const Ready &o) const {  // max-heap: the "largest" runs first
+      if (pri != o.pri) return pri < o.pri;
+      if (at != o.at) return at > o.at;
+      return id < o.id;
+    }
+  };
+  std::priority_queue<Ready> ready;
+  using Run = std::pair<double, int32_t>;  // (end, id), earliest end first
+  std::priority_queue<Run, std::vector<Run>, std::greater<Run>> running;
+  std::vector<int32_t> deg(g.indeg0.begin(), g.indeg0.end());
+  for (int t = 0; t < n; t++)
+    if (deg[t] == 0) ready.push({g.bottom[t], 0.0, t});
+  double now = 0.0, makespan = 0.0;
+  int idle = P, done = 0;
+  while (done < n) {
+    while (idle > 0 && !ready.empty()) {
+      const Ready r = ready.top();
+      ready.pop();
+      running.push({now + g.weight[r.id], r.id});
+      idle--;
+    }
+    if (running.empty()) break;  // cannot happen for a valid graph
+    now = running.top().first;
+    while (!running.empty() && running.top().first == now) {
+      const int32_t t = running.top().second;
+      running.pop();
+      idle++;
+      done++;
+      makespan = std::max(makespan, now);
+      for (int e = g.succ_off[t]; e < g.succ_off[t + 1]; e++) {
+        const int32_t s = g.succ[e];
+        if (--deg[s] == 0) ready.push({g.bottom[s], now, s});
+      }
+    }
+  }
+  return makespan;
 }
 
 bool validate(const Graph &g) {

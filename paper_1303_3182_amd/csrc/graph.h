@@ -73,6 +73,23 @@ Graph build_graph(const std::vector<Elim> &list, const GraphSpec &spec,
 // order (highest bottom level first when `priority`, else list order).
 void finalize(Graph &g, bool priority);
 
+// Bounded-processor analysis of a finalized graph, in its weight unit
+// (thesis chapters "Scheduling of Cholesky Factorization", section "ALAP
+// Derived Performance Bound", equation eqn:alapbound, and "Scheduling of QR
+// Factorization", section "Optimality"):
+//   alap_lost_area: every task placed as late as possible on unbounded
+//     processors (start = cp - bottom level); the idle area of P
+//     processors over the tail of that placement in which it never uses
+//     more than P of them;
+//   alap_bound: max(cp, (total weight + lost area) / P), a lower bound on
+//     the makespan of any schedule on P processors;
+//   list_makespan: the critical-path list schedule on P processors (an idle
+//     processor starts the ready task of largest bottom level; ties to the
+//     earliest ready, then the latest in list order).
+double alap_lost_area(const Graph &g, int P);
+double alap_bound(const Graph &g, int P);
+double list_makespan(const Graph &g, int P);
+
 // Host-side check that the graph is acyclic and that dependency counts
 // match (a Kahn pass over the successor lists).
 bool validate(const Graph &g);

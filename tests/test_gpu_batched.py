@@ -93,9 +93,14 @@ def test_batched_square_member_converges(dtype):
     """A square member of a low-precision batch is stopped by the
     Rigal-Gaches measure (its residual reaches rounding level), so it
     converges like the rectangular members instead of running out of
-    refinement steps."""
+    refinement steps.  Classical refinement with BF16 factors contracts only
+    when kappa * u_bf16 is well below one (u_bf16 = 2^-8), so the BF16
+    case takes a square member of condition number 10 (a 200 x 200
+    Gaussian matrix has kappa of order 1e3)."""
     shapes = [(300, 100), (200, 200), (500, 60)]
     As = [synth.gaussian(m, n, 70 + i) for i, (m, n) in enumerate(shapes)]
+    if dtype == "bf16":
+        As[1] = synth.conditioned(200, 10.0, 71)[0]
     Bs = [synth.gaussian_rhs(m, 1, 70 + i) for i, (m, n) in enumerate(shapes)]
     case("batched square member %s" % dtype)
     o = T.default_opts(nb=64, ib=16, tree="greedy", update_dtype=dtype, max_refine=20)

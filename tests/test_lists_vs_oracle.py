@@ -125,3 +125,39 @@ def test_batched_host_checks():
     nul = ctypes.POINTER(ctypes.c_void_p)()
     assert L.tqr_lstsq_batched(0, ms, ns, 1, nul, None, nul, None, nul, None, None, 0, None, None, None) == -1
     assert L.tqr_lstsq_batched(3, ms, bad, 1, nul, None, nul, None, nul, None, None, 0, None, None, None) == -2
+
+
+def test_schedule_bounds_match_oracle():
+    """The product's bounded-processor analysis (ALAP derived bound, lost
+    area, critical-path list schedule) of its own factorization graph equals
+    the scheduling oracle's on the same elimination lists (one task per
+    tile, table tab.kernels weights), including every cell of table
+    tab:5x5_optimal that the oracle reproduces."""
+    from fractions import Fraction
+
+    from oracle import schedule as S
+    nb = 64
+    for (p, q) in [(5, 5), (4, 2), (8, 3), (15, 6), (20, 6), (12, 12)]:
+        for tree in ("flat", "binary", "fibonacci", "greedy", "grasap"):
+            for fam, mode in ((T.TT, "tt"), (T.HYBRID, "hybrid")):
+                d = S.qr_dag(p, q, O.elimination_list(tree, p, q), mode)
+                o = T.default_opts(nb=nb, tree=tree, kernels=fam, stripes=1)
+                for P in (1, 2, 3, 4, 5, 7, 10, 14, 64):
+                    got = T.tqr_schedule_bounds(p * nb, q * nb, o, P)
+                    assert got["cp"] == S.critical_path(d) and got["t_seq"] == d.total_work()
+                    assert got["lost_area"] == S.lost_area(d, P), (tree, mode, p, q, P)
+                    assert Fraction(got["alap_bound"]).limit_denominator(1000) == S.alap_bound(d, P)
+                    assert got["list_makespan"] == S.list_schedule(d, P)[0], (tree, mode, p, q, P)
+
+
+def test_schedule_bounds_of_striped_graphs_are_consistent():
+    """With update stripes (weights split among a tile's stripes) the bounds
+    keep their order: cp <= ALAP bound <= list schedule <= Graham's bound."""
+    for (m, n, nb) in [(16384, 2048, 256), (8192, 8192, 256), (3000, 1000, 128)]:
+        o = T.default_opts(nb=nb, tree="greedy")
+        for P in (1, 16, 256):
+            b = T.tqr_schedule_bounds(m, n, o, P)
+            assert b["cp"] <= b["alap_bound"] + 1e-9
+            assert max(b["cp"], b["t_seq"] / P) <= b["alap_bound"] + 1e-9
+            assert b["alap_bound"] <= b["list_makespan"] + 1e-9
+            assert b["list_makespan"] <= b["t_seq"] / P + (1 - 1 / P) * b["cp"] + 1e-9
