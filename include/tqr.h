@@ -95,7 +95,8 @@ enum {
   TQR_E_WORKSPACE = -101,   /* workspace smaller than tqr_workspace_size   */
   TQR_E_UNSUPPORTED = -102, /* option combination not built                */
   TQR_E_NOMEM = -103,       /* library could not allocate its task tables  */
-  TQR_E_INTERNAL = -104     /* task graph failed its host-side validation  */
+  TQR_E_INTERNAL = -104,    /* task graph failed its host-side validation  */
+  TQR_E_SCRATCH = -105      /* too large for tqr_lstsq_noalloc's scratch   */
 };
 enum { TQR_INFO_TIMEOUT = -1000, TQR_INFO_NOCONV = -1001 };
 
@@ -275,6 +276,28 @@ int64_t tqr_tree_cp(int32_t tree, int32_t p, int32_t q, int32_t param, int32_t k
 /* Number of tasks and dependency edges of the executor's graph for the
  * given problem (factor only).  No GPU is touched. */
 int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, int64_t *nedges);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * least-squares solve of tqr_lstsq (same arguments and results, same
+ * kernels), with its workspace and task graphs placed in a device array of
+ * TQR_NOALLOC_SCRATCH_BYTES that the library defines statically; every GPU
+ * it runs on holds one such array until the process ends.  The call makes
+ * no hipMalloc / hipFree and no allocating library call on the device (its
+ * task graphs are built on the host, host memory, and cached per shape,
+ * then copied into the array on `stream` at every call).  Every call on one
+ * GPU uses that GPU's single array, so calls that overlap on one GPU (on
+ * different streams, or from several threads) race; calls ordered on one
+ * stream do not.  The array keeps the last call's contents; each call
+ * resets what must start at zero (executor counters, refinement report)
+ * on the stream.  Returns TQR_E_SCRATCH, and enqueues nothing, when the
+ * workspace (tqr_lstsq_work_size) plus the task graphs exceed the array;
+ * TQR_E_UNSUPPORTED for opts.tree = TQR_AUTO (the selector runs device
+ * work); otherwise as tqr_lstsq. */
+#define TQR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int tqr_lstsq_noalloc(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+                      int64_t ldb, double *X, int64_t ldx, const tqr_opts *o, int32_t *info,
+                      hipStream_t stream);
 
 /* Bounded-processor schedule analysis of the factorization's task graph
  * for the problem and options given (the graph tqr_factor runs: tree,

@@ -54,6 +54,7 @@ def lib():
             "tqr_solve_r": (ctypes.c_int, [i64, i64, vp, i64, vp, sz, i64, vp, i64, op, vp, vp]),
             "tqr_lstsq_work_size": (sz, [i64, i64, i64, op]),
             "tqr_lstsq": (ctypes.c_int, [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, op, vp, vp]),
+            "tqr_lstsq_noalloc": (ctypes.c_int, [i64, i64, i64, vp, i64, vp, i64, vp, i64, op, vp, vp]),
             "tqr_tree_list": (i64, [i32, i32, i32, i32, i32p, i32p, i32p, i64]),
             "tqr_tree_cp": (i64, [i32, i32, i32, i32, i32, i64p, i64p]),
             "tqr_graph_stats": (ctypes.c_int, [i64, i64, op, i64p, i64p]),
@@ -149,6 +150,11 @@ def tqr_lstsq_work_size(m, n, nrhs, opts=None):
 def tqr_lstsq(m, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, opts, info, stream):
     return _check(lib().tqr_lstsq(m, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes,
                                   _opts_ptr(opts), info, stream), "tqr_lstsq")
+
+
+def tqr_lstsq_noalloc(m, n, nrhs, A, lda, B, ldb, X, ldx, opts, info, stream):
+    return _check(lib().tqr_lstsq_noalloc(m, n, nrhs, A, lda, B, ldb, X, ldx, _opts_ptr(opts), info, stream),
+                  "tqr_lstsq_noalloc")
 
 
 def tqr_tree_list(tree, p, q, param=0):

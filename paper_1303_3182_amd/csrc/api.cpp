@@ -11,6 +11,7 @@
 #include <memory>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "graph.h"
@@ -317,7 +318,7 @@ size_t state_bytes(int64_t ntasks) {
 // Runs one plan on the device.
 int run_plan(int kind, int64_t m, int64_t n, double *A, int64_t lda, double *B, int64_t ldb,
              int64_t nrhs, void *T, size_t t_bytes, const Resolved &r, int32_t *info,
-             hipStream_t stream, const int32_t *skip = nullptr) {
+             hipStream_t stream, const int32_t *skip = nullptr, const DevicePlan *given = nullptr) {
   const int nb = r.nb;
   const int64_t p = cdiv(m, nb), q = cdiv(n, nb);
   const PlanKey key = make_key(kind, (int)p, (int)q, kind == PK_FACTOR ? 0 : nrhs, r);
@@ -329,8 +330,13 @@ int run_plan(int kind, int64_t m, int64_t n, double *A, int64_t lda, double *B, 
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return TQR_E_HIP;
   DevicePlan dp;
-  int rc = device_plan(key, *hp, dev, &dp);
-  if (rc) return rc;
+  if (given) {
+    if (given->ntasks != (int32_t)hp->g.tasks.size()) return TQR_E_INTERNAL;
+    dp = *given;
+  } else {
+    int rc = device_plan(key, *hp, dev, &dp);
+    if (rc) return rc;
+  }
   char *base = static_cast<char *>(T);
   ExecArgs a{};
   a.tasks = dp.tasks;
@@ -795,9 +801,12 @@ size_t tqr_lstsq_work_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o
   return ls_layout(m, n, nrhs, r).total;
 }
 
-int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
-              int64_t ldb, double *X, int64_t ldx, void *work, size_t work_bytes, const tqr_opts *o,
-              int32_t *info, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+int lstsq_args(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B, int64_t ldb,
+               const double *X, int64_t ldx) {
   if (m < 1) return -1;
   if (n < 1 || n > m) return -2;
   if (nrhs < 1) return -3;
@@ -807,12 +816,79 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
   if (ldb < m) return -7;
   if (!X) return -8;
   if (ldx < n) return -9;
-  if (!work) return -10;
-  Resolved r;
-  int rc = resolve(o, &r, m, n);
-  if (rc) return rc;
+  return TQR_OK;
+}
+
+// The plans one least-squares call runs: the fused solve, and with
+// low-precision updates the refinement's Q^T r and R solve (square) or
+// semi-normal-equation solve (rectangular).
+std::vector<int> lstsq_plan_kinds(int64_t m, int64_t n, const Resolved &r) {
+  std::vector<int> k = {PK_LSTSQ};
+  if (r.update_dtype != TQR_F64) {
+    if (m == n) {
+      k.push_back(PK_APPLY);
+      k.push_back(PK_SOLVE);
+    } else {
+      k.push_back(PK_SNE);
+    }
+  }
+  return k;
+}
+
+size_t plan_region_bytes(const Graph &g) {
+  return align_up(std::max<size_t>(g.tasks.size(), 1) * sizeof(Task)) +
+         align_up((g.tasks.size() + 1) * 4) + align_up(std::max<size_t>(g.succ.size(), 1) * 4) +
+         2 * align_up(std::max<size_t>(g.tasks.size(), 1) * 4);
+}
+
+// Copies a host plan into a device region (stream-ordered) and describes it.
+int place_plan(const Graph &g, char *dst, hipStream_t stream, DevicePlan *out) {
+  size_t off = 0;
+  auto put = [&](auto *&ptr, const auto &vec) -> bool {
+    using T = typename std::remove_reference<decltype(vec)>::type::value_type;
+    ptr = reinterpret_cast<T *>(dst + off);
+    off += align_up(std::max<size_t>(vec.size(), 1) * sizeof(T));
+    return vec.empty() || hipMemcpyAsync(ptr, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice,
+                                         stream) == hipSuccess;
+  };
+  Task *t = nullptr;
+  int32_t *so = nullptr, *su = nullptr, *i0 = nullptr, *r0 = nullptr;
+  if (!put(t, g.tasks) || !put(so, g.succ_off) || !put(su, g.succ) || !put(i0, g.indeg0) || !put(r0, g.ready0))
+    return TQR_E_HIP;
+  out->tasks = t;
+  out->succ_off = so;
+  out->succ = su;
+  out->indeg0 = i0;
+  out->ready0 = r0;
+  out->ntasks = (int32_t)g.tasks.size();
+  out->nready0 = (int32_t)g.ready0.size();
+  return TQR_OK;
+}
+
+// Body of tqr_lstsq.  With plan_area null the task graphs come from the
+// library's per-device plan cache; otherwise they are copied into
+// plan_area (on the stream) and nothing is allocated on the device.
+int lstsq_impl(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B, int64_t ldb,
+               double *X, int64_t ldx, void *work, size_t work_bytes, const Resolved &r, int32_t *info,
+               hipStream_t stream, char *plan_area) {
+  int rc = TQR_OK;
   const LsLayout L = ls_layout(m, n, nrhs, r);
   if (work_bytes < L.total) return TQR_E_WORKSPACE;
+  DevicePlan placed[3];
+  const DevicePlan *given[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (plan_area) {
+    const std::vector<int> kinds = lstsq_plan_kinds(m, n, r);
+    size_t off = 0;
+    for (size_t x = 0; x < kinds.size(); x++) {
+      const PlanKey key = make_key(kinds[x], (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), nrhs, r);
+      auto hp = host_plan(key);
+      if (!hp->valid) return TQR_E_INTERNAL;
+      rc = place_plan(hp->g, plan_area + off, stream, &placed[x]);
+      if (rc) return rc;
+      off += plan_region_bytes(hp->g);
+      given[kinds[x]] = &placed[x];
+    }
+  }
   char *w = static_cast<char *>(work);
   double *Ac = reinterpret_cast<double *>(w + L.ac);
   double *Bc = reinterpret_cast<double *>(w + L.bc);
@@ -828,7 +904,7 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
     if (refine_start(nullptr, P0, 1, stream) != hipSuccess) return TQR_E_HIP;
   }
   // factorization, Q^T B and R X = (Q^T B)(1:n) in one executor launch
-  rc = run_plan(PK_LSTSQ, m, n, Ac, m, Bc, m, nrhs, T, L.t_bytes, r, info, stream);
+  rc = run_plan(PK_LSTSQ, m, n, Ac, m, Bc, m, nrhs, T, L.t_bytes, r, info, stream, nullptr, given[PK_LSTSQ]);
   if (rc) return rc;
   if (r.update_dtype == TQR_F64) {
     if (hipMemcpy2DAsync(X, ldx * 8, Bc, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
@@ -871,10 +947,11 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
     if (refine_check(nullptr, P, 1, tol, it, stream) != hipSuccess) return TQR_E_HIP;
     if (it == r.max_refine) break;
     if (square) {
-      rc = run_plan(PK_APPLY, m, n, Ac, m, P.R, m, nrhs, T, L.t_bytes, r, info, stream, skip);
-      if (!rc) rc = run_plan(PK_SOLVE, m, n, Ac, m, P.R, m, nrhs, T, L.t_bytes, r, info, stream, skip);
+      rc = run_plan(PK_APPLY, m, n, Ac, m, P.R, m, nrhs, T, L.t_bytes, r, info, stream, skip, given[PK_APPLY]);
+      if (!rc)
+        rc = run_plan(PK_SOLVE, m, n, Ac, m, P.R, m, nrhs, T, L.t_bytes, r, info, stream, skip, given[PK_SOLVE]);
     } else {
-      rc = run_plan(PK_SNE, m, n, Ac, m, P.S, n, nrhs, T, L.t_bytes, r, info, stream, skip);
+      rc = run_plan(PK_SNE, m, n, Ac, m, P.S, n, nrhs, T, L.t_bytes, r, info, stream, skip, given[PK_SNE]);
     }
     if (rc) return rc;
     if (refine_update(nullptr, P, 1, n, nrhs, stream) != hipSuccess) return TQR_E_HIP;
@@ -884,6 +961,47 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
   if (hipMemcpy2DAsync(X, ldx * 8, xw, n * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return TQR_E_HIP;
   return TQR_OK;
+}
+
+}  // namespace
+
+namespace tqr {
+
+// The allocation-free least-squares solve (called by tqr_lstsq_noalloc with
+// its device's scratch array): the workspace and the task graphs share
+// `scratch`; TQR_E_SCRATCH when they do not fit.
+int lstsq_scratch(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+                  int64_t ldb, double *X, int64_t ldx, const tqr_opts *o, int32_t *info, hipStream_t stream,
+                  char *scratch, size_t scratch_bytes) {
+  int rc = lstsq_args(m, n, nrhs, A, lda, B, ldb, X, ldx);
+  if (rc) return rc;
+  if (o && o->tree == TQR_AUTO) return TQR_E_UNSUPPORTED;  // the selector runs device work
+  Resolved r;
+  rc = resolve(o, &r, m, n);
+  if (rc) return rc;
+  const LsLayout L = ls_layout(m, n, nrhs, r);
+  size_t plans = 0;
+  for (int kind : lstsq_plan_kinds(m, n, r))
+    plans += plan_region_bytes(host_plan(make_key(kind, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), nrhs, r))->g);
+  const size_t work = align_up(L.total);
+  if (work + plans > scratch_bytes) return TQR_E_SCRATCH;
+  return lstsq_impl(m, n, nrhs, A, lda, B, ldb, X, ldx, scratch, work, r, info, stream, scratch + work);
+}
+
+}  // namespace tqr
+
+extern "C" {
+
+int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+              int64_t ldb, double *X, int64_t ldx, void *work, size_t work_bytes, const tqr_opts *o,
+              int32_t *info, hipStream_t stream) {
+  int rc = lstsq_args(m, n, nrhs, A, lda, B, ldb, X, ldx);
+  if (rc) return rc;
+  if (!work) return -10;
+  Resolved r;
+  rc = resolve(o, &r, m, n);
+  if (rc) return rc;
+  return lstsq_impl(m, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, r, info, stream, nullptr);
 }
 
 size_t tqr_lstsq_batched_work_size(int32_t count, const int64_t *m, const int64_t *n, int64_t nrhs,
@@ -1399,6 +1517,8 @@ const char *tqr_strerror(int code) {
     case TQR_E_UNSUPPORTED: return "unsupported option combination";
     case TQR_E_NOMEM: return "out of device memory for task tables";
     case TQR_E_INTERNAL: return "task graph failed validation";
+    case TQR_E_SCRATCH:
+      return "problem too large for the allocation-free entry point's scratch (TQR_NOALLOC_SCRATCH_BYTES)";
     case TQR_INFO_TIMEOUT: return "device executor watchdog fired";
     case TQR_INFO_NOCONV: return "refinement did not converge";
     default: return code < 0 ? "illegal argument" : "R has an exactly zero diagonal entry";
