@@ -239,3 +239,126 @@ def alap_bound(d, P):
     """The ALAP derived bound T_P = max(cp, (T_seq + LA_P) / P), exact."""
     tseq = d.total_work()
     return max(Fraction(critical_path(d)), Fraction(tseq + lost_area(d, P), P))
+
+
+# ------------------------------------------------- tile Cholesky inversion
+CHOLINV_WEIGHTS = {"POTRF": 1, "TRSM": 3, "SYRK": 3, "GEMM": 6, "TRTRI": 1, "TRMM": 3, "LAUUM": 1}
+
+
+def cholinv_dag(t, inplace=True, order="UDU", pipelined=True, weights=None):
+    """Task graph of the tile Cholesky inversion of t x t tiles (lower), in
+    the loop order of algorithm alg:InPlace (chapter "Cholesky Inversion"):
+    step 1 the tile Cholesky factorization, step 2 the inversion of L, step
+    3 the product L^{-T} L^{-1}; tile (i,j) is one item updated in place.
+
+    `order` gives the direction of the innermost loop of each step (the
+    successive commutative GEMMs; section "Algorithmic study", loop
+    reversal): U increasing, D decreasing.  inplace=False is the variant
+    with array renaming: step 2 reads the tiles of L from a copy taken at
+    the end of step 1 and step 3 those of L^{-1} from a copy taken at the
+    end of step 2, so those reads carry no anti-dependence (the copies are
+    not tasks).  pipelined=False separates the steps: every task of a step
+    waits for every task of the step before.  weights: None counts tasks
+    (unit weights, as table table:criticalpath does); CHOLINV_WEIGHTS gives
+    flops in units of nb^3/3."""
+    d = Dag()
+    W = weights or {}
+
+    def w(kind):
+        return W.get(kind, 1)
+
+    def loop(rng, o):
+        return list(rng) if o == "U" else list(reversed(list(rng)))
+
+    step_tasks = []
+    barrier = set()
+    # the value of tile (i,j) at the end of the previous step: (writer task)
+    snapshot = {}
+
+    def add(name, reads=(), writes=(), copied=()):
+        t_ = d.add(name, w(name[0]), reads=reads, writes=writes)
+        d.preds[t_].update(barrier)
+        for it in copied:  # read from the renamed copy: true dependence only
+            if it in snapshot:
+                d.preds[t_].add(snapshot[it])
+        d.preds[t_].discard(t_)
+        step_tasks.append(t_)
+        return t_
+
+    def end_step():
+        nonlocal barrier
+        snapshot.clear()
+        snapshot.update(d._last_writer)
+        if not pipelined:
+            barrier = set(step_tasks)
+        step_tasks.clear()
+
+    def rd(i, j):
+        """(reads, copied) for a read of tile (i,j) of the previous step's
+        result."""
+        return ([], [(i, j)]) if not inplace else ([(i, j)], [])
+
+    # step 1: tile Cholesky factorization
+    for j in range(t):
+        for k in loop(range(j), order[0]):
+            add(("SYRK", j, k), reads=[(j, k)], writes=[(j, j)])
+        add(("POTRF", j), writes=[(j, j)])
+        for i in range(j + 1, t):
+            for k in loop(range(j), order[0]):
+                add(("GEMM", i, j, k), reads=[(i, k), (j, k)], writes=[(i, j)])
+        for i in range(j + 1, t):
+            add(("TRSM", i, j), reads=[(j, j)], writes=[(i, j)])
+    end_step()
+    # step 2: triangular inversion of L
+    for j in reversed(range(t)):
+        add(("TRTRI", j), writes=[(j, j)])
+        for i in reversed(range(j + 1, t)):
+            add(("TRMM", i, j, "L"), reads=[(i, i)], writes=[(i, j)])
+            for k in loop(range(j + 1, i), order[1]):
+                r_, c_ = rd(k, j)
+                add(("GEMM", i, j, k), reads=[(i, k)] + r_, writes=[(i, j)], copied=c_)
+            add(("TRMM", i, j, "R"), reads=[(j, j)], writes=[(i, j)])
+    end_step()
+    # step 3: product of the lower triangular matrices
+    for i in range(t):
+        for j in range(i):
+            r_, c_ = rd(i, i)
+            add(("TRMM", i, j, "T"), reads=r_, writes=[(i, j)], copied=c_)
+        add(("LAUUM", i), writes=[(i, i)])
+        for j in range(i):
+            for k in loop(range(i + 1, t), order[2]):
+                r1, c1 = rd(k, i)
+                r2, c2 = rd(k, j)
+                add(("GEMM", i, j, k), reads=r1 + r2, writes=[(i, j)], copied=c1 + c2)
+        for k in loop(range(i + 1, t), order[2]):
+            r_, c_ = rd(k, i)
+            add(("SYRK", i, k), reads=r_, writes=[(i, i)], copied=c_)
+    end_step()
+    return d
+
+
+def cholinv_step_cps(t, inplace=True, order="UDU"):
+    """Critical path (in tasks) of each step alone: the graph of the steps
+    separated, minus the path up to the previous step's end."""
+    out = []
+    prev = 0
+    for s in range(3):
+        d = cholinv_dag(t, inplace, order, pipelined=False)
+        # tasks of steps <= s
+        names = d.names
+        cnt = _step_counts(t)
+        upto = sum(cnt[:s + 1])
+        sub = Dag()
+        sub.names, sub.w = names[:upto], d.w[:upto]
+        sub.preds = [set(p) for p in d.preds[:upto]]
+        cp = critical_path(sub)
+        out.append(cp - prev)
+        prev = cp
+    return out
+
+
+def _step_counts(t):
+    s1 = t + t * (t - 1) // 2 * 2 + t * (t - 1) * (t - 2) // 6
+    s2 = t + t * (t - 1) + t * (t - 1) * (t - 2) // 6
+    s3 = t + t * (t - 1) // 2 * 2 + t * (t - 1) * (t - 2) // 6
+    return [s1, s2, s3]
