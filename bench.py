@@ -324,7 +324,15 @@ def gamma_ub(T, torch, np, m, n, nrhs, opts, run_once, tree_name):
         sel = kinds == k
         by_kind[names[k]] = {"tasks": int(sel.sum()), "mean_us": float(d[sel].mean() * 1e3),
                              "total_ms": float(d[sel].sum())}
-    return {"P": P, "T_units": units, "cp_units": cp_units,
+    # the ALAP derived bound (chapter "Scheduling of Cholesky
+    # Factorization", equation eqn:alapbound) and the critical-path list
+    # schedule of the executor's own factorization graph on P slots, in
+    # units and converted to time with the same per-slot rate
+    sb = T.tqr_schedule_bounds(m, n, opts, P)
+    sched = {k: sb[k] for k in ("cp", "t_seq", "lost_area", "alap_bound", "list_makespan")}
+    sched["alap_bound_ms"] = sb["alap_bound"] * unit / rate
+    sched["list_schedule_ms"] = sb["list_makespan"] * unit / rate
+    return {"P": P, "T_units": units, "cp_units": cp_units, "schedule_bounds_units": sched,
             "gamma_task_tflops_per_slot": rate / 1e9,
             "thesis_model": {"t_ub_ms": t_model, "gamma_ub": flops / (t_model / 1e3) / 1e12,
                              "bound": "T/P" if units / P >= cp_units else "cp"},
@@ -370,6 +378,7 @@ def run_square(args, np, torch, T, synth):
             rep = T.refine_report(w)
             res[dt] = {"ms_per_step": ms, "value": qr_flops(n, n) / (ms / 1e3) / 1e12, "executor_ms": kms,
                        "executor_launches_per_step": nl, "refine_steps": rep["iterations"],
+                       "gmres_steps": rep["gmres_steps"], "krylov_steps": rep["krylov_steps"],
                        "converged": rep["done"], "info": int(info.item()), "backward_error": be,
                        "equal_fp64_error": bool(be <= 50 * EPS and int(info.item()) == 0)}
             if dt == "f64" and fp64 is None:
@@ -377,8 +386,8 @@ def run_square(args, np, torch, T, synth):
                 if not args.no_gamma_ub:
                     gub = gamma_ub(T, torch, np, n, n, 1, o, lambda: T.lstsq(A, b, o, X=X, work=w, info=info),
                                    args.tree)
-            log("kappa %g %s: %.2f ms, be %.2e, refine %d, info %d" % (kappa, dt, ms, be, rep["iterations"],
-                                                                     int(info.item())))
+            log("kappa %g %s: %.2f ms, be %.2e, refine %d (gmres %d, krylov %d), info %d" %
+                (kappa, dt, ms, be, rep["iterations"], rep["gmres_steps"], rep["krylov_steps"], int(info.item())))
         for dt in args.mixed:
             res[dt]["speedup_vs_fp64"] = res["f64"]["ms_per_step"] / res[dt]["ms_per_step"]
         per_kappa["%g" % kappa] = res
@@ -410,6 +419,8 @@ def run_square(args, np, torch, T, synth):
         out["roofline"]["frac_of_gamma_ub"] = out["roofline"]["achieved"] / gub["measured_dag"]["gamma_ub"]
     if not args.no_c2:
         out["c2_trees"] = c2_trees(args, np, torch, T, synth)
+    if args.cholinv_n > 0:
+        out["cholinv"] = cholinv_leg(args, np, torch, T)
     if not args.no_cpu_baseline:
         A0, _, _ = synth.conditioned(n, args.kappas[0], 7)
         c = args.cpu_sample_cols
@@ -417,6 +428,47 @@ def run_square(args, np, torch, T, synth):
         out["cpu_baseline"] = oracle_qr_rate(A0[:, :c].copy(order="F"),
                                              "unblocked FP64 Householder QR of the first %d columns of the "
                                              "%dx%d kappa=%g matrix (%d x %d)" % (c, n, n, args.kappas[0], n, c))
+    return out
+
+
+def cholinv_leg(args, np, torch, T):
+    """Tile Cholesky inversion (chapter "Cholesky Inversion") of an n x n
+    SPD matrix, G G^T / n + I with G ~ N(0,1) (seeded), nb = 64, in place
+    and with array renaming: time per inversion (executor launch, HIP
+    events) and n^3 / t in TFLOP/s; accuracy as ||A X - I||_F / (||A||_F
+    ||X||_F) in FP64."""
+    n, nb = args.cholinv_n, 64
+    rng = np.random.default_rng(9)
+    G = rng.standard_normal((n, n))
+    A0 = G @ G.T / n + np.eye(n)
+    dev = torch.device("cuda:0")
+    Ad = T.colmajor(A0, dev)
+    A = Ad.clone()
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = {"workload": "tile Cholesky inversion of an %dx%d SPD matrix (G G^T/n + I, N(0,1), seed 9), nb=%d "
+                       "(%dx%d tiles), steps pipelined, UDU loop order" % (n, n, nb, -(-n // nb), -(-n // nb)),
+           "n": n, "nb": nb, "flops": float(n) ** 3}
+    for name, variant in (("in_place", T.CHOLINV_INPLACE), ("renamed", T.CHOLINV_RENAMED)):
+        nbytes = T.tqr_cholinv_work_size(n, nb, variant)
+        work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+        def step():
+            A.copy_(Ad)
+            T.cholinv(A, nb=nb, variant=variant, work=work, info=info)
+
+        ms, kms, _ = timed(step, max(3, args.steps // 2), 1, torch, T)
+        X = np.tril(A.cpu().numpy())
+        X = X + np.tril(X, -1).T
+        res = float(np.linalg.norm(A0 @ X - np.eye(n)) / (np.linalg.norm(A0) * np.linalg.norm(X)))
+        tasks, cp_tasks, cp_w = T.tqr_cholinv_graph_stats(-(-n // nb), variant)
+        out[name] = {"executor_ms": kms, "ms_per_step_with_copy": ms, "tflops": float(n) ** 3 / (kms / 1e3) / 1e12,
+                     "info": int(info.item()), "residual": res, "tasks": tasks,
+                     "critical_path_tasks": cp_tasks, "critical_path_units": cp_w}
+        log("cholinv %s n=%d: %.3f ms (%.2f TFLOP/s), residual %.2e" %
+            (name, n, kms, out[name]["tflops"], res))
+    out["roofline"] = {"bound": "alu", "achieved": out["renamed"]["tflops"], "peak": PEAK_FP64_MFMA,
+                       "unit": "TFLOP/s", "frac": out["renamed"]["tflops"] / PEAK_FP64_MFMA,
+                       "note": "FP64 FMA vector rate equals the FP64 matrix rate on this chip"}
     return out
 
 
@@ -516,6 +568,8 @@ def main():
     ap.add_argument("--cpu-sample-cols", type=int, default=256)
     ap.add_argument("--no-c2", action="store_true", help="skip the 16384x2048 five-tree comparison")
     ap.add_argument("--no-gamma-ub", action="store_true", help="skip the traced launch of the DAG bound")
+    ap.add_argument("--cholinv-n", type=int, default=4096,
+                    help="size of the tile Cholesky inversion leg of the default run (0: skip)")
     ap.add_argument("--max-refine", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed", nargs="*", default=["f32", "bf16"],

@@ -78,7 +78,7 @@ enum tqr_exec { TQR_EXEC_PERSISTENT = 0, TQR_EXEC_SEQUENTIAL = 1 };
 typedef struct tqr_opts {
   int32_t nb;           /* tile size: 32, 64, 128 or 256 (default 256)      */
   int32_t ib;           /* inner block: 16 or 32, divides nb (default 32)   */
-  int32_t tree;         /* enum tqr_tree (default TQR_GRASAP)               */
+  int32_t tree;         /* enum tqr_tree (default TQR_GREEDY)               */
   int32_t kernels;      /* enum tqr_kernels (default TQR_TT)                */
   int32_t param;        /* PlasmaTree BS / GrASAP i (default 0)             */
   int32_t update_dtype; /* enum tqr_dtype (default TQR_F64)                 */
@@ -86,8 +86,19 @@ typedef struct tqr_opts {
   int32_t stripes;      /* update tasks per tile (0: 1 up to nb 128, 4 at 256) */
   int32_t max_refine;   /* refinement steps for mixed precision (def. 10)   */
   int32_t priority;     /* 1 = critical-path-first ready order (default 1)  */
+  int32_t refine_method;/* enum tqr_refine (default TQR_REFINE_AUTO)        */
+  int32_t reserved;     /* 0                                                */
   double refine_tol;    /* refinement stop, relative backward error (0=auto)*/
 } tqr_opts;
+
+/* Refinement after low-precision updates (tqr_lstsq, one problem):
+ * AUTO takes classical steps and, for a square system with one right-hand
+ * side, switches to GMRES-based steps once a classical step fails to halve
+ * the backward error; CLASSICAL never switches; GMRES uses GMRES-based
+ * steps from the first (square, one right-hand side; else classical).  A
+ * GMRES-based step that fails to halve the backward error ends the
+ * refinement (info: TQR_INFO_NOCONV). */
+enum tqr_refine { TQR_REFINE_AUTO = 0, TQR_REFINE_CLASSICAL = 1, TQR_REFINE_GMRES = 2 };
 
 enum {
   TQR_OK = 0,
@@ -159,19 +170,29 @@ size_t tqr_lstsq_work_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o
  * valid once the stream has passed the call).  With update_dtype TQR_F64
  * only `done` = 0 and `iterations` = 0 are written.  Refinement (project
  * addition; the thesis treats FP64 only): square systems take classical
- * iterative refinement, x += R^{-1} (Q^T r)(1:n); rectangular ones
- * refinement of the semi-normal equations, x += R^{-1} R^{-T} A^T r; the
+ * iterative refinement, x += R^{-1} (Q^T r)(1:n), or GMRES-based steps
+ * (opts.refine_method): the correction solves A d = r by GMRES in FP64
+ * left-preconditioned by the computed factors, M^{-1} = R^{-1} Q^T, which
+ * converges where kappa(A) times the update precision's unit roundoff
+ * exceeds one and classical steps stall; rectangular systems take
+ * refinement of the semi-normal equations, x += R^{-1} R^{-T} A^T r.  The
  * residuals r = b - A x and A^T r are FP64 with compensated dot products.
  * Each iteration first tests the backward error of the current x
  * (square: ||r|| / (||A||_F ||x|| + ||b||); rectangular:
  * ||A^T r|| / (||A||_F ||r||)) against opts.refine_tol (0: 16 * 2^-52),
- * worst over the right-hand sides, and stops when it is met. */
+ * worst over the right-hand sides, and stops when it is met.  Unless the
+ * stream is being captured into a HIP graph, tqr_lstsq reads the report
+ * back after each test (it then returns once the refinement has finished)
+ * and enqueues no step after convergence; under capture it enqueues
+ * max_refine classical steps, each a no-op once `done` is set. */
 #define TQR_REFINE_HISTORY 24
 typedef struct tqr_refine_report {
   int32_t done;           /* 1: the tolerance was met                          */
   int32_t iterations;     /* corrections applied before the last test          */
   double backward_error;  /* measured at the last test (-1: none)              */
   double history[TQR_REFINE_HISTORY]; /* at each test (-1: not reached)       */
+  int32_t gmres_steps;    /* outer steps taken by GMRES (0: classical only)    */
+  int32_t krylov_steps;   /* GMRES iterations (applications of M^{-1} A) in all */
 } tqr_refine_report;
 int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
               int64_t ldb, double *X, int64_t ldx, void *work, size_t work_bytes,
@@ -298,6 +319,37 @@ int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, in
 int tqr_lstsq_noalloc(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
                       int64_t ldb, double *X, int64_t ldx, const tqr_opts *o, int32_t *info,
                       hipStream_t stream);
+
+/* ------------------------------------------------ tile Cholesky inversion
+ *
+ * A^{-1} of a symmetric positive definite n x n matrix, in place, by the
+ * thesis's tile algorithm (chapter "Cholesky Inversion", algorithm
+ * alg:InPlace): step 1 the tile Cholesky factorization A = L L^T, step 2
+ * W = L^{-1}, step 3 A^{-1} = W^T W, all three as one task graph (steps
+ * pipelined) run by one persistent executor launch.  A: device,
+ * column-major, lda >= n; only its lower triangle is read, and on return
+ * (stream-ordered) the lower triangle holds that of A^{-1}; the strict upper
+ * triangle is not touched.  nb: tile size, 32 or 64 (n need not be a
+ * multiple).  variant: TQR_CHOLINV_INPLACE (the algorithm as printed) or
+ * TQR_CHOLINV_RENAMED (array renaming, section "Algorithmic study": steps 2
+ * and 3 read L and L^{-1} from copies in `work`, which removes their
+ * anti-dependences and shortens the critical path), optionally |
+ * TQR_CHOLINV_UUU (every innermost GEMM loop upward; the default UDU runs
+ * step 2's downward, which the same section shows is shorter).  work:
+ * tqr_cholinv_work_size bytes of device memory (executor state, and the
+ * copies for the renamed variant).  info: NULL or a device int32 receiving
+ * 0, k > 0 when the leading minor of order k is not positive definite (the
+ * result is then undefined), or TQR_INFO_TIMEOUT.  Returns 0 or -i for an
+ * illegal i-th argument / a TQR_E_* code. */
+enum { TQR_CHOLINV_INPLACE = 0, TQR_CHOLINV_RENAMED = 1, TQR_CHOLINV_UUU = 2 };
+size_t tqr_cholinv_work_size(int64_t n, int32_t nb, int32_t variant);
+int tqr_cholinv(int64_t n, double *A, int64_t lda, int32_t nb, int32_t variant, void *work, size_t work_bytes,
+                int32_t *info, hipStream_t stream);
+
+/* Task count and critical path of the inversion's graph for t x t tiles,
+ * in tasks (table table:criticalpath counts tasks) and weighted (units of
+ * nb^3/3).  Host only. */
+int tqr_cholinv_graph_stats(int32_t t, int32_t variant, int64_t *ntasks, double *cp_tasks, double *cp_weighted);
 
 /* Bounded-processor schedule analysis of the factorization's task graph
  * for the problem and options given (the graph tqr_factor runs: tree,

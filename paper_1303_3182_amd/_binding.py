@@ -12,6 +12,7 @@ TREES = {"flat": FLAT, "binary": BINARY, "fibonacci": FIBONACCI, "greedy": GREED
 TT, HYBRID = 0, 1
 F64, F32, BF16 = 0, 1, 2
 EXEC_PERSISTENT, EXEC_SEQUENTIAL = 0, 1
+REFINE_AUTO, REFINE_CLASSICAL, REFINE_GMRES = 0, 1, 2
 
 
 class TqrError(RuntimeError):
@@ -23,7 +24,8 @@ class Opts(ctypes.Structure):
                 ("kernels", ctypes.c_int32), ("param", ctypes.c_int32),
                 ("update_dtype", ctypes.c_int32), ("exec", ctypes.c_int32),
                 ("stripes", ctypes.c_int32), ("max_refine", ctypes.c_int32),
-                ("priority", ctypes.c_int32), ("refine_tol", ctypes.c_double)]
+                ("priority", ctypes.c_int32), ("refine_method", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("refine_tol", ctypes.c_double)]
 
 
 _lib = None
@@ -59,6 +61,10 @@ def lib():
             "tqr_tree_cp": (i64, [i32, i32, i32, i32, i32, i64p, i64p]),
             "tqr_graph_stats": (ctypes.c_int, [i64, i64, op, i64p, i64p]),
             "tqr_schedule_bounds": (ctypes.c_int, [i64, i64, op, i32, ctypes.POINTER(ctypes.c_double)]),
+            "tqr_cholinv_work_size": (sz, [i64, i32, i32]),
+            "tqr_cholinv": (ctypes.c_int, [i64, vp, i64, i32, i32, vp, sz, vp, vp]),
+            "tqr_cholinv_graph_stats": (ctypes.c_int, [i32, i32, i64p, ctypes.POINTER(ctypes.c_double),
+                                                       ctypes.POINTER(ctypes.c_double)]),
             "tqr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "tqr_lstsq_batched_work_size": (sz, [i32, i64p, i64p, i64, op]),
             "tqr_lstsq_batched": (ctypes.c_int, [i32, i64p, i64p, i64, vpp, i64p, vpp, i64p, vpp, i64p, vp, sz, op,
@@ -116,6 +122,8 @@ def default_opts(**kw):
             v = {"tt": TT, "hybrid": HYBRID, "ts": HYBRID}[v]
         if k == "update_dtype" and isinstance(v, str):
             v = {"f64": F64, "f32": F32, "bf16": BF16}[v]
+        if k == "refine_method" and isinstance(v, str):
+            v = {"auto": REFINE_AUTO, "classical": REFINE_CLASSICAL, "gmres": REFINE_GMRES}[v]
         setattr(o, k, v)
     return o
 
@@ -201,6 +209,27 @@ def tqr_schedule_bounds(m, n, opts=None, P=1):
     out = (ctypes.c_double * 5)()
     _check(lib().tqr_schedule_bounds(m, n, _opts_ptr(opts), P, out), "tqr_schedule_bounds")
     return dict(zip(("cp", "t_seq", "lost_area", "alap_bound", "list_makespan"), list(out)))
+
+
+CHOLINV_INPLACE, CHOLINV_RENAMED, CHOLINV_UUU = 0, 1, 2
+
+
+def tqr_cholinv_work_size(n, nb=64, variant=CHOLINV_INPLACE):
+    return int(lib().tqr_cholinv_work_size(n, nb, variant))
+
+
+def tqr_cholinv(n, A, lda, nb, variant, work, work_bytes, info, stream):
+    return _check(lib().tqr_cholinv(n, A, lda, nb, variant, work, work_bytes, info, stream), "tqr_cholinv")
+
+
+def tqr_cholinv_graph_stats(t, variant=CHOLINV_INPLACE):
+    """(tasks, critical path in tasks, weighted critical path in nb^3/3) of
+    the inversion's graph for t x t tiles (host only)."""
+    nt = ctypes.c_int64()
+    cpt, cpw = ctypes.c_double(), ctypes.c_double()
+    _check(lib().tqr_cholinv_graph_stats(t, variant, ctypes.byref(nt), ctypes.byref(cpt), ctypes.byref(cpw)),
+           "tqr_cholinv_graph_stats")
+    return nt.value, cpt.value, cpw.value
 
 
 def debug_timing(enable):

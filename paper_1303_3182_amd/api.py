@@ -93,11 +93,19 @@ def refine_report(work):
     """The refinement report that tqr_lstsq leaves at the start of its
     workspace: dict(done, iterations, backward_error, history)."""
     import numpy as np
-    raw = work[:8 + 8 + 8 * B.REFINE_HISTORY].cpu().numpy().tobytes()
+    rec = 8 + 8 + 8 * B.REFINE_HISTORY + 8
+    raw = work[:rec].cpu().numpy().tobytes()
+    return _report(raw)
+
+
+def _report(raw):
+    import numpy as np
     done, iters = np.frombuffer(raw[:8], dtype=np.int32)
-    vals = np.frombuffer(raw[8:], dtype=np.float64)
+    vals = np.frombuffer(raw[8:8 + 8 + 8 * B.REFINE_HISTORY], dtype=np.float64)
+    gm, ks = np.frombuffer(raw[16 + 8 * B.REFINE_HISTORY:24 + 8 * B.REFINE_HISTORY], dtype=np.int32)
     hist = [float(v) for v in vals[1:] if v >= 0.0]
-    return {"done": int(done), "iterations": int(iters), "backward_error": float(vals[0]), "history": hist}
+    return {"done": int(done), "iterations": int(iters), "backward_error": float(vals[0]), "history": hist,
+            "gmres_steps": int(gm), "krylov_steps": int(ks)}
 
 
 def _i64arr(v):
@@ -171,13 +179,21 @@ def autotune_batched(As, Bs, opts, Xs=None, work=None):
 def refine_reports(work, count):
     """The per-problem refinement reports at the start of a batched workspace."""
     import numpy as np
-    rec = 8 + 8 + 8 * B.REFINE_HISTORY
+    rec = 8 + 8 + 8 * B.REFINE_HISTORY + 8
     raw = work[:rec * count].cpu().numpy().tobytes()
-    out = []
-    for x in range(count):
-        r = raw[rec * x:rec * (x + 1)]
-        done, iters = np.frombuffer(r[:8], dtype=np.int32)
-        vals = np.frombuffer(r[8:], dtype=np.float64)
-        out.append({"done": int(done), "iterations": int(iters), "backward_error": float(vals[0]),
-                    "history": [float(v) for v in vals[1:] if v >= 0.0]})
-    return out
+    return [_report(raw[rec * x:rec * (x + 1)]) for x in range(count)]
+
+
+def cholinv(A, nb=64, variant=0, work=None, info=None):
+    """In-place inverse of the SPD matrix whose lower triangle A holds
+    (column-major float64 CUDA tensor): on return A's lower triangle holds
+    that of A^{-1}.  variant: CHOLINV_INPLACE / CHOLINV_RENAMED (| CHOLINV_UUU)."""
+    n = A.shape[0]
+    if work is None:
+        nbytes = B.tqr_cholinv_work_size(n, nb, variant)
+        if nbytes == 0:
+            raise B.TqrError("invalid size/options for cholinv")
+        work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    B.tqr_cholinv(n, A.data_ptr(), _ld(A), nb, variant, work.data_ptr(), work.numel(),
+                  None if info is None else info.data_ptr(), _stream())
+    return A

@@ -21,6 +21,9 @@
 #include "tqr_types.h"
 
 namespace tqr {
+bool cholinv_nb_supported(int nb);
+int cholinv_occupancy(int nb);
+hipError_t launch_cholinv(const ExecArgs &a, int nb, int grid, int32_t *info, hipStream_t s);
 hipError_t launch_exec(const ExecArgs &a, int mode, int grid, const int32_t *order, int32_t *info,
                        hipStream_t s);
 int exec_occupancy(int nb, int ib);
@@ -43,7 +46,8 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // solve in one graph (factor, Q^T B and R X = B with the right-hand sides as
 // extra tile columns, so B's updates overlap the factorization).
 // PK_SNE: R^T Z = B then R X = Z in one graph (semi-normal equations).
-enum PlanKind { PK_FACTOR = 0, PK_APPLY = 1, PK_SOLVE = 2, PK_LSTSQ = 3, PK_SOLVET = 4, PK_SNE = 5 };
+enum PlanKind { PK_FACTOR = 0, PK_APPLY = 1, PK_SOLVE = 2, PK_LSTSQ = 3, PK_SOLVET = 4, PK_SNE = 5,
+                PK_CHOLINV = 6 /* tile Cholesky inversion: p = q = t, family = renaming, tree = UUU */ };
 bool solve_kind(int k) { return k == PK_SOLVE || k == PK_SOLVET || k == PK_SNE; }
 
 struct PlanKey {
@@ -84,6 +88,18 @@ std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
     if (it != g_host.end()) return it->second;
   }
   auto hp = std::make_shared<HostPlan>();
+  if (k.kind == PK_CHOLINV) {
+    hp->g = build_cholinv_graph(k.p, k.family == 0, k.tree == 0);
+    finalize(hp->g, true);
+    hp->valid = validate(hp->g);
+    hp->g.preds.clear();
+    hp->g.preds.shrink_to_fit();
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_host.find(k);
+    if (it != g_host.end()) return it->second;
+    g_host[k] = hp;
+    return hp;
+  }
   GraphSpec spec;
   spec.p = k.p;
   spec.q = k.q;
@@ -169,7 +185,7 @@ int64_t spin_limit_ticks(int dev) {
 }
 
 struct Resolved {
-  int nb, ib, tree, param, family, stripes, priority, exec, update_dtype, max_refine;
+  int nb, ib, tree, param, family, stripes, priority, exec, update_dtype, max_refine, refine_method;
   double refine_tol;
 };
 
@@ -277,6 +293,8 @@ int resolve(const tqr_opts *o, Resolved *r, int64_t m = 0, int64_t n = 0) {
   r->update_dtype = x.update_dtype;
   r->max_refine = x.max_refine < 0 ? 0 : x.max_refine;
   r->refine_tol = x.refine_tol;
+  if (x.refine_method < TQR_REFINE_AUTO || x.refine_method > TQR_REFINE_GMRES) return TQR_E_UNSUPPORTED;
+  r->refine_method = x.refine_method;
   const int wc = chunk_width(r->nb, r->ib);
   int s = x.stripes;
   // default: one update task per tile up to nb = 128, four 64-column
@@ -400,7 +418,8 @@ int64_t plan_tasks(int kind, int64_t m, int64_t n, int64_t nrhs, const Resolved 
 // plan), and, with low-precision updates, the refinement buffers: X, the
 // residual R (m x nrhs), A^T R (n x nrhs) and the residual partial sums.
 struct LsLayout {
-  size_t report, ac, bc, t, t_bytes, xw, rw, sw, part, total;
+  size_t report, ac, bc, t, t_bytes, xw, rw, sw, part, gm, total;
+  bool gmres;  // GMRES-based refinement possible (square, one right-hand side)
 };
 
 LsLayout ls_layout(int64_t m, int64_t n, int64_t nrhs, const Resolved &r) {
@@ -431,7 +450,13 @@ LsLayout ls_layout(int64_t m, int64_t n, int64_t nrhs, const Resolved &r) {
     L.sw = off;
     off += align_up((size_t)n * nrhs * 8);
     L.part = off;
-    off += align_up(refine_partial_bytes(m, n, nrhs));
+    off += align_up(std::max(refine_partial_bytes(m, n, nrhs),
+                             (size_t)kFroBlocks * sizeof(double) + gmres_partial_bytes(n)));
+    L.gmres = (m == n && nrhs == 1);
+    if (L.gmres) {
+      L.gm = off;
+      off += align_up(gmres_bytes(n, kGmresMax));
+    }
   }
   L.total = off;
   return L;
@@ -709,7 +734,7 @@ void tqr_default_opts(tqr_opts *o) {
   std::memset(o, 0, sizeof(*o));
   o->nb = 256;
   o->ib = 32;
-  o->tree = TQR_GRASAP;
+  o->tree = TQR_GREEDY;
   o->kernels = TQR_TT;
   o->param = 0;
   o->update_dtype = TQR_F64;
@@ -717,6 +742,7 @@ void tqr_default_opts(tqr_opts *o) {
   o->stripes = 0;
   o->max_refine = 10;
   o->priority = 1;
+  o->refine_method = TQR_REFINE_AUTO;
   o->refine_tol = 0.0;
 }
 
@@ -912,12 +938,18 @@ int lstsq_impl(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
     return TQR_OK;
   }
   // Low-precision updates: refine X in FP64 against the caller's A and B.
-  // Square systems use classical refinement, d = R^{-1} (Q^T r)(1:n);
-  // rectangular ones the semi-normal equations with the computed R,
-  // d = R^{-1} R^{-T} A^T r, whose fixed point satisfies A^T r = 0 exactly
-  // (classical refinement would stop at a point with A^T r of the size of
-  // the factorization error times r).  Every iteration is enqueued; the
-  // kernels of the iterations after convergence return at once.
+  // Square systems use classical refinement, d = R^{-1} (Q^T r)(1:n), or
+  // GMRES on A d = r preconditioned by M^{-1} = R^{-1} Q^T; rectangular
+  // ones the semi-normal equations with the computed R, d = R^{-1} R^{-T}
+  // A^T r, whose fixed point satisfies A^T r = 0 exactly (classical
+  // refinement would stop at a point with A^T r of the size of the
+  // factorization error times r).  Unless the stream is being captured,
+  // the report is read back after each test: no step is enqueued after
+  // convergence, a classical step that fails to halve the backward error
+  // switches a square one-right-hand-side system to GMRES (method AUTO),
+  // and a GMRES step that fails to halve it ends the refinement.  Under
+  // capture every step is enqueued and the kernels of the steps after
+  // convergence return at once.
   const bool square = (m == n);
   RefProb P{};
   P.A = A;
@@ -939,6 +971,26 @@ int lstsq_impl(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
   P.square = square ? 1 : 0;
   const double tol = r.refine_tol > 0.0 ? r.refine_tol : 16.0 * 2.220446049250313e-16;
   const int32_t *skip = &rep->done;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  const bool poll = hipStreamIsCapturing(stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone;
+  const bool can_gmres = poll && L.gmres && r.refine_method != TQR_REFINE_CLASSICAL;
+  bool use_gmres = can_gmres && r.refine_method == TQR_REFINE_GMRES;
+  bool last_gmres = false;  // the previous step was a GMRES step
+  GmArgs G{};
+  if (can_gmres)
+    G = gmres_args(w + L.gm, n, kGmresMax, A, lda, P.X, P.R, w + L.part + kFroBlocks * sizeof(double), rep,
+                   1e-4);
+  // M^{-1} z = R^{-1} (Q^T z)(1:n) in place on the m x nrhs buffer z
+  auto precondition = [&](double *z) -> int {
+    int e = run_plan(PK_APPLY, m, n, Ac, m, z, m, nrhs, T, L.t_bytes, r, info, stream, skip, given[PK_APPLY]);
+    if (!e) e = run_plan(PK_SOLVE, m, n, Ac, m, z, m, nrhs, T, L.t_bytes, r, info, stream, skip, given[PK_SOLVE]);
+    return e;
+  };
+  tqr_refine_report host{};
+  auto read_back = [&](void *dst, const void *src, size_t bytes) -> bool {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream) == hipSuccess &&
+           hipStreamSynchronize(stream) == hipSuccess;
+  };
   if (hipMemcpy2DAsync(P.X, n * 8, Bc, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return TQR_E_HIP;
   if (refine_fro(nullptr, P, 1, stream) != hipSuccess) return TQR_E_HIP;
@@ -946,10 +998,38 @@ int lstsq_impl(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
     if (refine_residual(nullptr, P, 1, m, n, stream) != hipSuccess) return TQR_E_HIP;
     if (refine_check(nullptr, P, 1, tol, it, stream) != hipSuccess) return TQR_E_HIP;
     if (it == r.max_refine) break;
+    if (poll) {
+      if (!read_back(&host, rep, sizeof(host))) return TQR_E_HIP;
+      if (host.done) break;
+      const bool stalled = it >= 1 && it < kRefineHistory && !(host.history[it] <= 0.5 * host.history[it - 1]);
+      // a GMRES step that fails to halve the error: the factors are too far
+      // from A for this method; stop (info reports NOCONV) rather than
+      // spend the remaining steps
+      if (stalled && use_gmres && last_gmres) break;
+      if (stalled && can_gmres) use_gmres = true;
+    }
+    last_gmres = use_gmres;
+    if (use_gmres) {
+      // one GMRES cycle on A d = r: z = M^{-1} r, then Krylov steps with
+      // z = M^{-1} A v_j until the preconditioned residual has dropped by
+      // the cycle's tolerance; x += V y
+      rc = precondition(P.R);
+      if (rc) return rc;
+      if (gmres_init(G, stream) != hipSuccess) return TQR_E_HIP;
+      for (int j = 0; j < kGmresMax; j++) {
+        if (gmres_matvec(G, j, stream) != hipSuccess) return TQR_E_HIP;
+        rc = precondition(P.R);
+        if (rc) return rc;
+        if (gmres_arnoldi(G, j, stream) != hipSuccess) return TQR_E_HIP;
+        GmState gs{};
+        if (!read_back(&gs, G.st, sizeof(gs))) return TQR_E_HIP;
+        if (gs.inner_done) break;
+      }
+      if (gmres_update(G, stream) != hipSuccess) return TQR_E_HIP;
+      continue;
+    }
     if (square) {
-      rc = run_plan(PK_APPLY, m, n, Ac, m, P.R, m, nrhs, T, L.t_bytes, r, info, stream, skip, given[PK_APPLY]);
-      if (!rc)
-        rc = run_plan(PK_SOLVE, m, n, Ac, m, P.R, m, nrhs, T, L.t_bytes, r, info, stream, skip, given[PK_SOLVE]);
+      rc = precondition(P.R);
     } else {
       rc = run_plan(PK_SNE, m, n, Ac, m, P.S, n, nrhs, T, L.t_bytes, r, info, stream, skip, given[PK_SNE]);
     }
@@ -1388,6 +1468,137 @@ int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, in
   if (ntasks) *ntasks = (int64_t)hp->g.tasks.size();
   if (nedges) *nedges = hp->g.nedges;
   return hp->valid ? TQR_OK : TQR_E_INTERNAL;
+}
+
+// ------------------------------------------------ tile Cholesky inversion
+}  // extern "C"
+
+namespace {
+
+PlanKey cholinv_key(int64_t n, int nb, int variant) {
+  PlanKey k{};
+  k.kind = PK_CHOLINV;
+  k.p = k.q = (int)cdiv(n, nb);
+  k.family = variant & TQR_CHOLINV_RENAMED ? 1 : 0;
+  k.tree = variant & TQR_CHOLINV_UUU ? 1 : 0;
+  k.stripes = k.stripes_b = 1;
+  k.priority = 1;
+  return k;
+}
+
+struct CholLayout {
+  size_t state, l0, w0, total;
+};
+
+CholLayout cholinv_layout(int64_t n, int nb, int variant) {
+  CholLayout L{};
+  const int64_t nt = (int64_t)host_plan(cholinv_key(n, nb, variant))->g.tasks.size();
+  L.state = 0;
+  size_t off = align_up(state_bytes(nt));
+  if (variant & TQR_CHOLINV_RENAMED) {
+    L.l0 = off;
+    off += align_up((size_t)n * n * 8);
+    L.w0 = off;
+    off += align_up((size_t)n * n * 8);
+  }
+  L.total = off;
+  return L;
+}
+
+std::map<std::pair<int, int>, int> g_chol_grid;
+
+}  // namespace
+
+extern "C" {
+
+size_t tqr_cholinv_work_size(int64_t n, int32_t nb, int32_t variant) {
+  if (n < 1 || !cholinv_nb_supported(nb) || variant < 0 || variant > 3) return 0;
+  return cholinv_layout(n, nb, variant).total;
+}
+
+int tqr_cholinv(int64_t n, double *A, int64_t lda, int32_t nb, int32_t variant, void *work, size_t work_bytes,
+                int32_t *info, hipStream_t stream) {
+  if (n < 1) return -1;
+  if (!A) return -2;
+  if (lda < n) return -3;
+  if (!cholinv_nb_supported(nb)) return -4;
+  if (variant < 0 || variant > 3) return -5;
+  if (!work) return -6;
+  const PlanKey key = cholinv_key(n, nb, variant);
+  auto hp = host_plan(key);
+  if (!hp->valid) return TQR_E_INTERNAL;
+  const CholLayout L = cholinv_layout(n, nb, variant);
+  if (work_bytes < L.total) return TQR_E_WORKSPACE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TQR_E_HIP;
+  DevicePlan dp;
+  int rc = device_plan(key, *hp, dev, &dp);
+  if (rc) return rc;
+  int grid = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_chol_grid.find({dev, nb});
+    if (it != g_chol_grid.end()) grid = it->second;
+  }
+  if (!grid) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    grid = cus * cholinv_occupancy(nb);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_chol_grid[{dev, nb}] = grid;
+  }
+  char *w = static_cast<char *>(work);
+  ExecArgs a{};
+  a.tasks = dp.tasks;
+  a.succ_off = dp.succ_off;
+  a.succ = dp.succ;
+  a.indeg0 = dp.indeg0;
+  a.ready0 = dp.ready0;
+  a.ntasks = dp.ntasks;
+  a.nready0 = dp.nready0;
+  a.ctl = reinterpret_cast<ExecCtl *>(w + L.state);
+  a.queue = reinterpret_cast<int32_t *>(w + L.state + align_up(sizeof(ExecCtl)));
+  a.indeg = reinterpret_cast<int32_t *>(w + L.state + align_up(sizeof(ExecCtl)) +
+                                        align_up((size_t)std::max<int32_t>(a.ntasks, 1) * 4));
+  a.prob.A = A;
+  a.prob.lda = lda;
+  a.prob.m = n;
+  a.prob.n = n;
+  // copies of L and L^{-1} (renamed variant): the tile kernels take them from
+  // the Problem's B and Tf pointers, leading dimension ldb
+  a.prob.B = (variant & TQR_CHOLINV_RENAMED) ? reinterpret_cast<double *>(w + L.l0) : nullptr;
+  a.prob.Tf = (variant & TQR_CHOLINV_RENAMED) ? reinterpret_cast<double *>(w + L.w0) : nullptr;
+  a.prob.ldb = n;
+  a.prob.p = a.prob.q = key.p;
+  a.prob.singular = &a.ctl->pad[0];
+  a.nb = nb;
+  a.spin_limit = spin_limit_ticks(dev);
+  a.trace = g_trace;
+  a.trace_cap = g_trace_cap;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (g_timing && hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess)
+    hipEventRecord(ev0, stream);
+  const hipError_t e = launch_cholinv(a, nb, grid, info, stream);
+  if (ev1) {
+    hipEventRecord(ev1, stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_events.emplace_back(ev0, ev1);
+  }
+  return e == hipSuccess ? TQR_OK : TQR_E_HIP;
+}
+
+int tqr_cholinv_graph_stats(int32_t t, int32_t variant, int64_t *ntasks, double *cp_tasks, double *cp_weighted) {
+  if (t < 1) return -1;
+  if (variant < 0 || variant > 3) return -2;
+  const bool inplace = !(variant & TQR_CHOLINV_RENAMED), udu = !(variant & TQR_CHOLINV_UUU);
+  Graph gw = build_cholinv_graph(t, inplace, udu, false);
+  Graph gu = build_cholinv_graph(t, inplace, udu, true);
+  finalize(gw, true);
+  if (!validate(gw)) return TQR_E_INTERNAL;
+  if (ntasks) *ntasks = (int64_t)gw.tasks.size();
+  if (cp_tasks) *cp_tasks = gu.cp;
+  if (cp_weighted) *cp_weighted = gw.cp;
+  return TQR_OK;
 }
 
 int tqr_schedule_bounds(int64_t m, int64_t n, const tqr_opts *o, int32_t P, double *out) {

@@ -1,0 +1,340 @@
+// Tile kernels of the tile Cholesky inversion (thesis chapter "Cholesky
+// Inversion", algorithm alg:InPlace) and the persistent executor that runs
+// its task graph.  FP64, gfx950, NB x NB tiles of a column-major matrix.
+//
+// Every task stages its operand tiles in LDS (column-major, padded stride),
+// computes there or in registers, and writes its result tile: all global
+// reads of a task precede its writes, so a task whose output aliases an
+// input (the in-place TRMMs, LAUUM) needs no other care.  Only the lower
+// triangle of the matrix is read or written.  Tiles past n are padded: zero
+// off the diagonal, one on the diagonal of a diagonal tile (so the Cholesky
+// factor and the inverse of a padded diagonal tile are padded with the
+// identity); stores skip the padding.
+//
+// Products C = beta Z + alpha op(X) op(Y): each thread holds an RB x RB
+// block of C in registers (rows tr + 16a, columns tc + 16b), reading X and
+// Y from LDS; on this chip FP64 FMA runs at the FP64 matrix rate, so the
+// plain FMA formulation loses nothing to the matrix cores.
+#include <hip/hip_runtime.h>
+
+#include "exec_loop.h"
+#include "tqr_types.h"
+
+namespace tqr {
+
+namespace {
+
+constexpr int CT = 256;  // threads per workgroup
+
+template <int NB>
+struct CholSmem {
+  static constexpr int LD = NB + 1;
+  double X[NB * LD];
+  double Y[NB * LD];
+  double Z[NB * LD];
+  int task;
+};
+
+enum LoadMode { LD_FULL = 0, LD_LOWER = 1, LD_DIAG = 2 };
+
+// dst = tile (rows x cols valid) of src; LD_LOWER zeroes the strict upper
+// triangle; LD_DIAG also puts ones on the padded part of the diagonal.
+template <int NB>
+__device__ __forceinline__ void load_tile(const double *__restrict__ src, int64_t ld, int rows, int cols,
+                                          double *dst, int mode) {
+  constexpr int LD = CholSmem<NB>::LD;
+  for (int idx = threadIdx.x; idx < NB * NB; idx += CT) {
+    const int r = idx % NB, c = idx / NB;
+    double v = 0.0;
+    if (r < rows && c < cols && (mode == LD_FULL || r >= c)) v = src[(int64_t)c * ld + r];
+    if (mode == LD_DIAG && r == c && (r >= rows || c >= cols)) v = 1.0;
+    dst[c * LD + r] = v;
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void store_tile(double *__restrict__ dst, int64_t ld, int rows, int cols,
+                                           const double *src, bool lower) {
+  constexpr int LD = CholSmem<NB>::LD;
+  for (int idx = threadIdx.x; idx < NB * NB; idx += CT) {
+    const int r = idx % NB, c = idx / NB;
+    if (r < rows && c < cols && (!lower || r >= c)) dst[(int64_t)c * ld + r] = src[c * LD + r];
+  }
+}
+
+// C = beta Z + alpha op(X) op(Y) (op = transpose when TX / TY), written to
+// dst (rows x cols valid; lower triangle only when `lower`), and to copy
+// when given.  X, Y, Z are in LDS.
+template <int NB, bool TX, bool TY>
+__device__ __forceinline__ void product(const CholSmem<NB> &sm, double alpha, double beta, double *dst,
+                                        int64_t ld, int rows, int cols, bool lower, double *copy,
+                                        int64_t ldc) {
+  constexpr int LD = CholSmem<NB>::LD;
+  constexpr int RB = NB / 16;
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  double acc[RB][RB];
+#pragma unroll
+  for (int a = 0; a < RB; a++)
+#pragma unroll
+    for (int b = 0; b < RB; b++) acc[a][b] = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < NB; k++) {
+    double xv[RB], yv[RB];
+#pragma unroll
+    for (int a = 0; a < RB; a++) {
+      const int r = tr + 16 * a;
+      xv[a] = TX ? sm.X[r * LD + k] : sm.X[k * LD + r];
+    }
+#pragma unroll
+    for (int b = 0; b < RB; b++) {
+      const int c = tc + 16 * b;
+      yv[b] = TY ? sm.Y[k * LD + c] : sm.Y[c * LD + k];
+    }
+#pragma unroll
+    for (int a = 0; a < RB; a++)
+#pragma unroll
+      for (int b = 0; b < RB; b++) acc[a][b] = fma(xv[a], yv[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < RB; a++)
+#pragma unroll
+    for (int b = 0; b < RB; b++) {
+      const int r = tr + 16 * a, c = tc + 16 * b;
+      const double v = (beta != 0.0 ? beta * sm.Z[c * LD + r] : 0.0) + alpha * acc[a][b];
+      if (r < rows && c < cols && (!lower || r >= c)) {
+        dst[(int64_t)c * ld + r] = v;
+        if (copy) copy[(int64_t)c * ldc + r] = v;
+      }
+    }
+}
+
+// Cholesky factor of the tile in Z (lower, in place), right-looking, one
+// column per step.  A non-positive (or NaN) pivot records the 1-based
+// global index base + c + 1 of the first such column in *notpd.
+template <int NB>
+__device__ __forceinline__ void potrf_lds(CholSmem<NB> &sm, int base, int32_t *notpd) {
+  constexpr int LD = CholSmem<NB>::LD;
+  double *Z = sm.Z;
+  for (int c = 0; c < NB; c++) {
+    __syncthreads();  // the previous column's trailing update is complete
+    const double d = Z[c * LD + c];
+    const bool ok = d > 0.0;
+    const double piv = ok ? sqrt(d) : __builtin_nan("");
+    if (!ok && threadIdx.x == 0) atomicMin(notpd, base + c + 1);
+    __syncthreads();  // every thread has read the pivot
+    if (threadIdx.x < NB && (int)threadIdx.x > c) Z[c * LD + threadIdx.x] /= piv;
+    if (threadIdx.x == 0) Z[c * LD + c] = piv;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NB * NB; idx += CT) {
+      const int r = idx % NB, s = idx / NB;
+      if (s > c && r >= s) Z[s * LD + r] = fma(-Z[c * LD + r], Z[c * LD + s], Z[s * LD + r]);
+    }
+  }
+  __syncthreads();
+}
+
+// Z <- Z L^{-T} with L (lower) in X: column c of the result is
+// (Z(:,c) - sum_{k<c} result(:,k) L(c,k)) / L(c,c), right-looking.
+template <int NB>
+__device__ __forceinline__ void trsm_lds(CholSmem<NB> &sm) {
+  constexpr int LD = CholSmem<NB>::LD;
+  double *Z = sm.Z;
+  const double *L = sm.X;
+  for (int c = 0; c < NB; c++) {
+    if (threadIdx.x < NB) Z[c * LD + threadIdx.x] /= L[c * LD + c];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NB * NB; idx += CT) {
+      const int r = idx % NB, s = idx / NB;
+      if (s > c) Z[s * LD + r] = fma(-Z[c * LD + r], L[c * LD + s], Z[s * LD + r]);
+    }
+    __syncthreads();
+  }
+}
+
+// Z <- L^{-1} for L (lower) in Z, in place, from the last column: W(c,c) =
+// 1/L(c,c), W(r,c) = -(sum_{c<k<=r} W(r,k) L(k,c)) W(c,c), r > c.
+template <int NB>
+__device__ __forceinline__ void trtri_lds(CholSmem<NB> &sm) {
+  constexpr int LD = CholSmem<NB>::LD;
+  double *Z = sm.Z;
+  const int r = threadIdx.x;
+  for (int c = NB - 1; c >= 0; c--) {
+    const double wcc = 1.0 / Z[c * LD + c];
+    double v = 0.0;
+    if (r < NB && r > c) {
+      for (int k = c + 1; k <= r; k++) v = fma(Z[k * LD + r], Z[c * LD + k], v);
+      v = -v * wcc;
+    }
+    __syncthreads();  // column c of L read by every thread
+    if (r < NB && r > c) Z[c * LD + r] = v;
+    if (r == c) Z[c * LD + c] = wcc;
+    __syncthreads();
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void run_chol_task(const Problem &p, const Task &t, CholSmem<NB> &sm) {
+  const int64_t lda = p.lda;
+  const int64_t n = p.n;
+  auto tile = [&](double *base, int64_t ld, int i, int j) { return base + (int64_t)j * NB * ld + (int64_t)i * NB; };
+  auto dim = [&](int i) { return (int)min((int64_t)NB, n - (int64_t)i * NB); };
+  // copies of L (end of step 1) and of L^{-1} (end of step 2), for the
+  // variant with array renaming; null in place
+  double *L0 = p.B, *W0 = p.Tf;
+  const int64_t ldc = p.ldb;
+  const int i = t.i, j = t.j, k = t.k;
+  const int kind = t.kind;
+  // source of a step-2 (step-3) read of tile (r, c): the copy when renamed
+  auto src2 = [&](int r, int c) { return L0 ? tile(L0, ldc, r, c) : tile(p.A, lda, r, c); };
+  auto src3 = [&](int r, int c) { return W0 ? tile(W0, ldc, r, c) : tile(p.A, lda, r, c); };
+  auto ld2 = [&]() { return L0 ? ldc : lda; };
+  auto ld3 = [&]() { return W0 ? ldc : lda; };
+  switch (kind) {
+    case K_POTRF: {  // A(j,j) <- chol(A(j,j))
+      load_tile<NB>(tile(p.A, lda, j, j), lda, dim(j), dim(j), sm.Z, LD_DIAG);
+      __syncthreads();
+      potrf_lds<NB>(sm, j * NB, p.singular);
+      store_tile<NB>(tile(p.A, lda, j, j), lda, dim(j), dim(j), sm.Z, true);
+      if (L0) store_tile<NB>(tile(L0, ldc, j, j), ldc, dim(j), dim(j), sm.Z, true);
+      break;
+    }
+    case K_CTRSM: {  // A(i,j) <- A(i,j) L(j,j)^{-T}
+      load_tile<NB>(tile(p.A, lda, j, j), lda, dim(j), dim(j), sm.X, LD_DIAG);
+      load_tile<NB>(tile(p.A, lda, i, j), lda, dim(i), dim(j), sm.Z, LD_FULL);
+      __syncthreads();
+      trsm_lds<NB>(sm);
+      store_tile<NB>(tile(p.A, lda, i, j), lda, dim(i), dim(j), sm.Z, false);
+      if (L0) store_tile<NB>(tile(L0, ldc, i, j), ldc, dim(i), dim(j), sm.Z, false);
+      break;
+    }
+    case K_CSYRK: {  // A(j,j) <- A(j,j) - A(j,k) A(j,k)^T
+      load_tile<NB>(tile(p.A, lda, j, j), lda, dim(j), dim(j), sm.Z, LD_LOWER);
+      load_tile<NB>(tile(p.A, lda, j, k), lda, dim(j), dim(k), sm.X, LD_FULL);
+      load_tile<NB>(tile(p.A, lda, j, k), lda, dim(j), dim(k), sm.Y, LD_FULL);
+      __syncthreads();
+      product<NB, false, true>(sm, -1.0, 1.0, tile(p.A, lda, j, j), lda, dim(j), dim(j), true, nullptr, 0);
+      break;
+    }
+    case K_CGEMM: {  // A(i,j) <- A(i,j) - A(i,k) A(j,k)^T
+      load_tile<NB>(tile(p.A, lda, i, j), lda, dim(i), dim(j), sm.Z, LD_FULL);
+      load_tile<NB>(tile(p.A, lda, i, k), lda, dim(i), dim(k), sm.X, LD_FULL);
+      load_tile<NB>(tile(p.A, lda, j, k), lda, dim(j), dim(k), sm.Y, LD_FULL);
+      __syncthreads();
+      product<NB, false, true>(sm, -1.0, 1.0, tile(p.A, lda, i, j), lda, dim(i), dim(j), false, nullptr, 0);
+      break;
+    }
+    case K_TRTRI: {  // A(j,j) <- L(j,j)^{-1}
+      load_tile<NB>(tile(p.A, lda, j, j), lda, dim(j), dim(j), sm.Z, LD_DIAG);
+      __syncthreads();
+      trtri_lds<NB>(sm);
+      store_tile<NB>(tile(p.A, lda, j, j), lda, dim(j), dim(j), sm.Z, true);
+      if (W0) store_tile<NB>(tile(W0, ldc, j, j), ldc, dim(j), dim(j), sm.Z, true);
+      break;
+    }
+    case K_TRMML: {  // A(i,j) <- A(i,i) A(i,j), A(i,i) = L(i,i)^{-1}
+      load_tile<NB>(tile(p.A, lda, i, i), lda, dim(i), dim(i), sm.X, LD_LOWER);
+      load_tile<NB>(tile(p.A, lda, i, j), lda, dim(i), dim(j), sm.Y, LD_FULL);
+      __syncthreads();
+      product<NB, false, false>(sm, 1.0, 0.0, tile(p.A, lda, i, j), lda, dim(i), dim(j), false, nullptr, 0);
+      break;
+    }
+    case K_IGEMM: {  // A(i,j) <- A(i,j) + A(i,k) L(k,j)
+      load_tile<NB>(tile(p.A, lda, i, j), lda, dim(i), dim(j), sm.Z, LD_FULL);
+      load_tile<NB>(tile(p.A, lda, i, k), lda, dim(i), dim(k), sm.X, LD_FULL);
+      load_tile<NB>(src2(k, j), ld2(), dim(k), dim(j), sm.Y, LD_FULL);
+      __syncthreads();
+      product<NB, false, false>(sm, 1.0, 1.0, tile(p.A, lda, i, j), lda, dim(i), dim(j), false, nullptr, 0);
+      break;
+    }
+    case K_TRMMR: {  // A(i,j) <- -A(i,j) A(j,j), A(j,j) = L(j,j)^{-1}
+      load_tile<NB>(tile(p.A, lda, i, j), lda, dim(i), dim(j), sm.X, LD_FULL);
+      load_tile<NB>(tile(p.A, lda, j, j), lda, dim(j), dim(j), sm.Y, LD_LOWER);
+      __syncthreads();
+      product<NB, false, false>(sm, -1.0, 0.0, tile(p.A, lda, i, j), lda, dim(i), dim(j), false,
+                                W0 ? tile(W0, ldc, i, j) : nullptr, ldc);
+      break;
+    }
+    case K_TRMMT: {  // A(i,j) <- W(i,i)^T A(i,j)
+      load_tile<NB>(src3(i, i), ld3(), dim(i), dim(i), sm.X, LD_LOWER);
+      load_tile<NB>(tile(p.A, lda, i, j), lda, dim(i), dim(j), sm.Y, LD_FULL);
+      __syncthreads();
+      product<NB, true, false>(sm, 1.0, 0.0, tile(p.A, lda, i, j), lda, dim(i), dim(j), false, nullptr, 0);
+      break;
+    }
+    case K_LAUUM: {  // A(i,i) <- A(i,i)^T A(i,i), lower triangle
+      load_tile<NB>(tile(p.A, lda, i, i), lda, dim(i), dim(i), sm.X, LD_LOWER);
+      load_tile<NB>(tile(p.A, lda, i, i), lda, dim(i), dim(i), sm.Y, LD_LOWER);
+      __syncthreads();
+      product<NB, true, false>(sm, 1.0, 0.0, tile(p.A, lda, i, i), lda, dim(i), dim(i), true, nullptr, 0);
+      break;
+    }
+    case K_PGEMM: {  // A(i,j) <- A(i,j) + W(k,i)^T W(k,j)
+      load_tile<NB>(tile(p.A, lda, i, j), lda, dim(i), dim(j), sm.Z, LD_FULL);
+      load_tile<NB>(src3(k, i), ld3(), dim(k), dim(i), sm.X, LD_FULL);
+      load_tile<NB>(src3(k, j), ld3(), dim(k), dim(j), sm.Y, LD_FULL);
+      __syncthreads();
+      product<NB, true, false>(sm, 1.0, 1.0, tile(p.A, lda, i, j), lda, dim(i), dim(j), false, nullptr, 0);
+      break;
+    }
+    case K_PSYRK: {  // A(i,i) <- A(i,i) + W(k,i)^T W(k,i), lower triangle
+      load_tile<NB>(tile(p.A, lda, i, i), lda, dim(i), dim(i), sm.Z, LD_LOWER);
+      load_tile<NB>(src3(k, i), ld3(), dim(k), dim(i), sm.X, LD_FULL);
+      load_tile<NB>(src3(k, i), ld3(), dim(k), dim(i), sm.Y, LD_FULL);
+      __syncthreads();
+      product<NB, true, false>(sm, 1.0, 1.0, tile(p.A, lda, i, i), lda, dim(i), dim(i), true, nullptr, 0);
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+template <int NB>
+__global__ void chol_reset(ExecArgs a) {
+  executor_reset(a);
+}
+
+template <int NB>
+__global__ __launch_bounds__(CT, 1) void exec_cholinv(ExecArgs a) {
+  __shared__ CholSmem<NB> sm;
+  if (a.skip && *a.skip) return;
+  executor_loop(a, &sm.task, [&](const Task &t) { run_chol_task<NB>(a.prob, t, sm); });
+}
+
+__global__ void chol_finish(ExecArgs a, int32_t *info) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int e = a.ctl->error;
+    const int z = *a.prob.singular;
+    if (info) *info = (e != 0) ? e : (z != 0x7fffffff ? z : 0);
+  }
+}
+
+template <int NB>
+hipError_t launch_nb(const ExecArgs &a, int grid, int32_t *info, hipStream_t s) {
+  const int rgrid = (int)((a.ntasks + 255) / 256);
+  hipLaunchKernelGGL(chol_reset<NB>, dim3(rgrid < 1 ? 1 : (rgrid > 1024 ? 1024 : rgrid)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(exec_cholinv<NB>, dim3(grid), dim3(CT), 0, s, a);
+  hipLaunchKernelGGL(chol_finish, dim3(1), dim3(64), 0, s, a, info);
+  return hipGetLastError();
+}
+
+template <int NB>
+int occupancy_nb() {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, exec_cholinv<NB>, CT, 0) != hipSuccess) return 1;
+  return b < 1 ? 1 : b;
+}
+
+}  // namespace
+
+bool cholinv_nb_supported(int nb) { return nb == 32 || nb == 64; }
+
+int cholinv_occupancy(int nb) { return nb == 32 ? occupancy_nb<32>() : occupancy_nb<64>(); }
+
+hipError_t launch_cholinv(const ExecArgs &a, int nb, int grid, int32_t *info, hipStream_t s) {
+  if (nb == 32) return launch_nb<32>(a, grid, info, s);
+  if (nb == 64) return launch_nb<64>(a, grid, info, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace tqr

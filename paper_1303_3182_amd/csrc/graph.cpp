@@ -426,6 +426,102 @@ void finalize(Graph &g, bool priority) {
   for (int t = 0; t < n; t++) g.order[t] = t;
 }
 
+// --------------------------------------------- tile Cholesky inversion
+Graph build_cholinv_graph(int t, bool inplace, bool udu, bool unit_weights) {
+  Graph g;
+  std::vector<ItemState> tiles((size_t)t * t), l0((size_t)t * t), w0((size_t)t * t);
+  auto A = [&](int i, int j) { return &tiles[(size_t)i * t + j]; };
+  auto L0 = [&](int i, int j) { return &l0[(size_t)i * t + j]; };
+  auto W0 = [&](int i, int j) { return &w0[(size_t)i * t + j]; };
+  auto weight = [&](int kind) -> double {
+    if (unit_weights) return 1.0;
+    switch (kind) {
+      case K_POTRF: case K_TRTRI: case K_LAUUM: return 1.0;
+      case K_CGEMM: case K_IGEMM: case K_PGEMM: return 6.0;
+      default: return 3.0;  // TRSM, SYRK, TRMM
+    }
+  };
+  auto emit = [&](int kind, int i, int j, int k, std::vector<ItemState *> rd, std::vector<ItemState *> wr) {
+    const int32_t id = (int32_t)g.tasks.size();
+    std::vector<int32_t> pr;
+    for (ItemState *it : rd)
+      if (it->writer >= 0) pr.push_back(it->writer);
+    for (ItemState *it : wr) {
+      if (it->writer >= 0) pr.push_back(it->writer);
+      for (int32_t r : it->readers) pr.push_back(r);
+    }
+    std::sort(pr.begin(), pr.end());
+    pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+    const double w = weight(kind);
+    double start = 0.0;
+    for (int32_t x : pr) start = std::max(start, g.finish[x]);
+    g.finish.push_back(start + w);
+    g.cp = std::max(g.cp, start + w);
+    g.nedges += (int64_t)pr.size();
+    for (ItemState *it : rd) it->readers.push_back(id);
+    for (ItemState *it : wr) {
+      it->writer = id;
+      it->readers.clear();
+    }
+    Task tk{};
+    tk.kind = kind;
+    tk.i = i;
+    tk.piv = i;
+    tk.j = j;
+    tk.k = k;
+    g.tasks.push_back(tk);
+    g.preds.push_back(std::move(pr));
+    g.weight.push_back(w);
+  };
+  // step 1: for each column j, the SYRKs into A(j,j), POTRF(j), the GEMMs
+  // below it, the TRSMs (the last writer of each tile also fills L's copy)
+  for (int j = 0; j < t; j++) {
+    for (int k = 0; k < j; k++) emit(K_CSYRK, j, j, k, {A(j, k)}, {A(j, j)});
+    if (inplace)
+      emit(K_POTRF, j, j, j, {}, {A(j, j)});
+    else
+      emit(K_POTRF, j, j, j, {}, {A(j, j), L0(j, j)});
+    for (int i = j + 1; i < t; i++)
+      for (int k = 0; k < j; k++) emit(K_CGEMM, i, j, k, {A(i, k), A(j, k)}, {A(i, j)});
+    for (int i = j + 1; i < t; i++) {
+      if (inplace)
+        emit(K_CTRSM, i, j, j, {A(j, j)}, {A(i, j)});
+      else
+        emit(K_CTRSM, i, j, j, {A(j, j)}, {A(i, j), L0(i, j)});
+    }
+  }
+  // step 2: W = L^{-1}, columns from the last; row i of column j is
+  // W(i,i) L(i,j), plus W(i,k) L(k,j) over j < k < i, times -W(j,j)
+  for (int j = t - 1; j >= 0; j--) {
+    if (inplace)
+      emit(K_TRTRI, j, j, j, {}, {A(j, j)});
+    else
+      emit(K_TRTRI, j, j, j, {}, {A(j, j), W0(j, j)});
+    for (int i = t - 1; i > j; i--) {
+      emit(K_TRMML, i, j, i, {A(i, i)}, {A(i, j)});
+      for (int x = 0; x < i - j - 1; x++) {
+        const int k = udu ? i - 1 - x : j + 1 + x;
+        emit(K_IGEMM, i, j, k, {A(i, k), inplace ? A(k, j) : L0(k, j)}, {A(i, j)});
+      }
+      if (inplace)
+        emit(K_TRMMR, i, j, j, {A(j, j)}, {A(i, j)});
+      else
+        emit(K_TRMMR, i, j, j, {A(j, j)}, {A(i, j), W0(i, j)});
+    }
+  }
+  // step 3: A^{-1} = W^T W, row block i: W(i,i)^T W(i,j), W(i,i)^T W(i,i),
+  // plus W(k,i)^T W(k,j) and W(k,i)^T W(k,i) over k > i
+  auto Wsrc = [&](int i, int j) { return inplace ? A(i, j) : W0(i, j); };
+  for (int i = 0; i < t; i++) {
+    for (int j = 0; j < i; j++) emit(K_TRMMT, i, j, i, {Wsrc(i, i)}, {A(i, j)});
+    emit(K_LAUUM, i, i, i, {}, {A(i, i)});
+    for (int j = 0; j < i; j++)
+      for (int k = i + 1; k < t; k++) emit(K_PGEMM, i, j, k, {Wsrc(k, i), Wsrc(k, j)}, {A(i, j)});
+    for (int k = i + 1; k < t; k++) emit(K_PSYRK, i, i, k, {Wsrc(k, i)}, {A(i, i)});
+  }
+  return g;
+}
+
 // ------------------------------------------------- bounded processors
 double alap_lost_area(const Graph &g, int P) {
   const int n = (int)g.tasks.size();

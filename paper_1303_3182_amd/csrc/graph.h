@@ -73,6 +73,20 @@ Graph build_graph(const std::vector<Elim> &list, const GraphSpec &spec,
 // order (highest bottom level first when `priority`, else list order).
 void finalize(Graph &g, bool priority);
 
+// Task graph of the tile Cholesky inversion of t x t tiles (thesis chapter
+// "Cholesky Inversion", algorithm alg:InPlace: step 1 the tile Cholesky
+// factorization, step 2 the inversion of L, step 3 the product
+// L^{-T} L^{-1}), in the algorithm's loop order with the steps pipelined
+// (every task waits only for the data it needs).  Items: tile (i,j) of the
+// lower triangle, updated in place.  inplace = false is the variant with
+// array renaming: the last writer of a tile in step 1 (step 2) also writes a
+// copy of it, and step 2 (step 3) reads L (L^{-1}) from those copies, so
+// those reads carry no anti-dependences.  udu: the innermost loop of step 2
+// runs downward (loop order UDU, the shorter critical path), else upward
+// (UUU).  Weights in units of nb^3/3 (POTRF, TRTRI, LAUUM 1; TRSM, SYRK,
+// TRMM 3; GEMM 6); unit_weights counts tasks instead.
+Graph build_cholinv_graph(int t, bool inplace, bool udu, bool unit_weights = false);
+
 // Bounded-processor analysis of a finalized graph, in its weight unit
 // (thesis chapters "Scheduling of Cholesky Factorization", section "ALAP
 // Derived Performance Bound", equation eqn:alapbound, and "Scheduling of QR

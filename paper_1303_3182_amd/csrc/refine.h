@@ -63,4 +63,44 @@ hipError_t refine_update(const RefProb *tab, const RefProb &one, int count, int6
 hipError_t refine_finish(const RefProb *tab, const RefProb &one, int count, int32_t noconv, hipStream_t s);
 hipError_t copy_batch(const CopyDesc *tab, int count, int64_t max_elems, hipStream_t s);
 
+// ------------------------------------------------ GMRES refinement (gmres.hip)
+constexpr int kGmresMax = 64;  // Krylov directions per outer step, at most
+
+// Device state of the GMRES cycle of one square problem.
+struct GmState {
+  int32_t j;            // directions built in the current cycle
+  int32_t inner_done;   // the cycle has converged (or reached its limit)
+  double beta;          // ||M^{-1} r|| at the cycle's start
+  double resid;         // preconditioned residual estimate |g(j)|
+};
+
+struct GmArgs {
+  const double *A;  // the caller's FP64 matrix (n x n, lda)
+  int64_t lda, n;
+  double *V;        // n x (kmax + 1) Krylov basis
+  double *H;        // (kmax + 1) x kmax Hessenberg matrix, column-major
+  double *cs, *sn, *gv;  // Givens rotations and the rotated right-hand side
+  double *x;        // iterate (n)
+  double *z;        // work vector: operand of M^{-1} (length >= n)
+  double *part;     // matrix-vector partial sums (gmres_partial_bytes)
+  GmState *st;
+  RefineState *rep;  // the refinement's report: every kernel returns once rep->done
+                     // is set; rep->gmres_steps / krylov_steps count the work
+  double tol;       // relative reduction of the preconditioned residual per cycle
+  int32_t kmax;
+  int32_t pad_;
+};
+
+size_t gmres_bytes(int64_t n, int kmax);
+size_t gmres_partial_bytes(int64_t n);
+GmArgs gmres_args(void *mem, int64_t n, int kmax, const double *A, int64_t lda, double *x, double *z,
+                  void *partial, RefineState *rep, double tol);
+// a cycle: gmres_init (z = M^{-1} r given), then per step j: z = A v_j
+// (gmres_matvec), z <- M^{-1} z (the executor), gmres_arnoldi; then
+// gmres_update (x += V y)
+hipError_t gmres_init(const GmArgs &g, hipStream_t s);
+hipError_t gmres_matvec(const GmArgs &g, int j, hipStream_t s);
+hipError_t gmres_arnoldi(const GmArgs &g, int j, hipStream_t s);
+hipError_t gmres_update(const GmArgs &g, hipStream_t s);
+
 }  // namespace tqr

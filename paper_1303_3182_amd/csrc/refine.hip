@@ -216,6 +216,8 @@ __global__ void start(const RefProb *tab, RefProb one, int count) {
     P.st->iterations = 0;
     P.st->backward_error = -1.0;
     for (int i = 0; i < kRefineHistory; i++) P.st->history[i] = -1.0;
+    P.st->gmres_steps = 0;
+    P.st->krylov_steps = 0;
   }
 }
 

@@ -17,7 +17,21 @@ enum Kind : int32_t {
   K_GEMM = 7,   // X(i,j) <- X(i,j) - R(i,k) X(k,j)
   K_TRSMT = 8,  // X(k,j) <- R(k,k)^{-T} X(k,j)
   K_GEMMT = 9,  // X(i,j) <- X(i,j) - R(k,i)^T X(k,j), i > k
-  K_COUNT = 10
+  // tile Cholesky inversion (chapter "Cholesky Inversion", algorithm
+  // alg:InPlace), lower triangle in place; W = L^{-1}
+  K_POTRF = 10,  // step 1: A(j,j) <- chol(A(j,j))
+  K_CTRSM = 11,  //         A(i,j) <- A(i,j) L(j,j)^{-T}
+  K_CSYRK = 12,  //         A(j,j) <- A(j,j) - A(j,k) A(j,k)^T
+  K_CGEMM = 13,  //         A(i,j) <- A(i,j) - A(i,k) A(j,k)^T
+  K_TRTRI = 14,  // step 2: A(j,j) <- L(j,j)^{-1}
+  K_TRMML = 15,  //         A(i,j) <- W(i,i) A(i,j)
+  K_IGEMM = 16,  //         A(i,j) <- A(i,j) + A(i,k) L(k,j)
+  K_TRMMR = 17,  //         A(i,j) <- -A(i,j) W(j,j)
+  K_TRMMT = 18,  // step 3: A(i,j) <- W(i,i)^T A(i,j)
+  K_LAUUM = 19,  //         A(i,i) <- W(i,i)^T W(i,i)
+  K_PGEMM = 20,  //         A(i,j) <- A(i,j) + W(k,i)^T W(k,j)
+  K_PSYRK = 21,  //         A(i,i) <- A(i,i) + W(k,i)^T W(k,i)
+  K_COUNT = 22
 };
 
 // One task of the executor's graph.  Tile coordinates are 0-based; column

@@ -10,6 +10,9 @@ V^T, Haar U and V, log-spaced s; b = A x + 1e-6 N(0,1)):
 - the solution (FP64, or refined after FP32 / BF16 updates) must meet the
   FP64 bar: normwise backward error (Rigal-Gaches, by the oracle in
   extended precision) <= 50 eps.
+FP32 at kappa 1e8 (kappa u_fp32 ~ 6 before the growth of the factorization
+error with n): classical steps stall and the GMRES-based steps do not
+reach the bar at this size; the outcome must be reported truthfully.
 Ragged least-squares batch at the ranges of the batched workload (m up to
 8192, n up to 512): every member's backward error (Stewart's bound) <= 50 eps
 and, for a sample of members, x against the oracle's x."""
@@ -61,6 +64,24 @@ def test_square_8192(dtype, kappa):
     assert be <= 50 * EPS, (be / EPS, rep)
     if dtype != "f64":
         assert rep["done"] == 1 and rep["iterations"] >= 1, rep
+
+
+def test_square_8192_fp32_kappa_1e8_is_reported():
+    A0, x0, b0 = synth.conditioned(N, 1e8, 7)
+    o = T.default_opts(nb=NB, ib=32, tree="greedy", update_dtype="f32", max_refine=20)
+    case("square 8192 f32 kappa=1e8: lstsq")
+    work = T.lstsq_workspace(N, N, 1, o)
+    info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    X = T.lstsq(T.colmajor(A0), T.colmajor(b0[:, None]), o, work=work, info=info)
+    torch.cuda.synchronize()
+    rep = T.refine_report(work)
+    case("square 8192 f32 kappa=1e8: report %s" % rep)
+    be = H.ls_backward_error(A0, b0, X[:, 0].cpu().numpy())
+    assert rep["gmres_steps"] >= 1  # classical steps stalled and GMRES was tried
+    if int(info.item()) == 0:
+        assert rep["done"] == 1 and be <= 50 * EPS
+    else:
+        assert int(info.item()) == -1001 and rep["done"] == 0 and be > 16 * EPS
 
 
 def _batch_c4(count, seed):

@@ -92,6 +92,65 @@ def test_refined_square_conditioned(dtype, kappa):
     assert np.linalg.norm(x - xo) <= 100 * kappa * EPS * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("dtype,kappa", [("f32", 1e8)])
+def test_gmres_refinement_where_classical_stalls(dtype, kappa):
+    """kappa times the update precision's unit roundoff (2^-24 for FP32)
+    above one: classical steps stall, and the AUTO method switches to GMRES
+    preconditioned by the low-precision factors, which reaches the FP64
+    bar."""
+    n, nb = 1024, 128
+    case("gmres refinement %s kappa=%g n=%d" % (dtype, kappa, n))
+    A0, x0, b0 = synth.conditioned(n, kappa, 5)
+    o = T.default_opts(nb=nb, tree="greedy", update_dtype=dtype, max_refine=20)
+    X, info, rep = _lstsq(A0, b0[:, None], o)
+    case("gmres refinement %s kappa=%g: report %s" % (dtype, kappa, rep))
+    assert info == 0 and rep["done"] == 1, (info, rep)
+    assert rep["gmres_steps"] >= 1 and rep["krylov_steps"] >= rep["gmres_steps"], rep
+    x = X[:, 0]
+    assert H.ls_backward_error(A0, b0, x) <= 50 * EPS
+    Ro, Vo, tau = H.qr(A0)
+    xo = H.back_substitute(Ro, H.apply_qt(Vo, tau, b0)[:n])
+    assert np.linalg.norm(x - xo) <= 100 * kappa * EPS * np.linalg.norm(xo)
+    # the classical method alone on the same system (reported, and never a
+    # false pass: when it stops short, info says so)
+    oc = T.default_opts(nb=nb, tree="greedy", update_dtype=dtype, max_refine=20, refine_method="classical")
+    Xc, infoc, repc = _lstsq(A0, b0[:, None], oc)
+    assert repc["gmres_steps"] == 0
+    assert (infoc == 0) == (repc["done"] == 1) and (infoc in (0, -1001)), (infoc, repc)
+    if infoc == 0:
+        assert H.ls_backward_error(A0, b0, Xc[:, 0]) <= 50 * EPS
+
+
+@pytest.mark.parametrize("kappa", [1e3, 1e4, 1e5])
+def test_gmres_beyond_its_reach_is_reported(kappa):
+    """BF16 updates (u_bf16 = 2^-8) at kappa 1e3..1e5: the factors may be
+    too far from A for restarted GMRES(64) to converge.  Whatever happens,
+    the outcome is reported truthfully: info 0 only with the FP64 bar met
+    (checked by the oracle), else TQR_INFO_NOCONV with the measured error
+    above the tolerance."""
+    n, nb = 1024, 128
+    case("gmres bf16 kappa=%g n=%d" % (kappa, n))
+    A0, x0, b0 = synth.conditioned(n, kappa, 5)
+    o = T.default_opts(nb=nb, tree="greedy", update_dtype="bf16", max_refine=6)
+    X, info, rep = _lstsq(A0, b0[:, None], o)
+    case("gmres bf16 kappa=%g: info %d report %s" % (kappa, info, rep))
+    be = H.ls_backward_error(A0, b0, X[:, 0])
+    if info == 0:
+        assert rep["done"] == 1 and be <= 50 * EPS
+    else:
+        assert info == -1001 and rep["done"] == 0 and be > 16 * EPS and rep["backward_error"] > 16 * EPS
+
+
+def test_gmres_method_from_the_first_step():
+    n, nb = 700, 64
+    case("gmres from the start n=%d" % n)
+    A0, x0, b0 = synth.conditioned(n, 1e3, 6)
+    o = T.default_opts(nb=nb, tree="fibonacci", update_dtype="f32", max_refine=10, refine_method="gmres")
+    X, info, rep = _lstsq(A0, b0[:, None], o)
+    assert info == 0 and rep["done"] == 1 and rep["gmres_steps"] == rep["iterations"] >= 1, rep
+    assert H.ls_backward_error(A0, b0, X[:, 0]) <= 50 * EPS
+
+
 def test_fp64_lstsq_report_untouched_by_refinement():
     A0 = synth.gaussian(300, 100, 1)
     B0 = synth.gaussian_rhs(300, 1, 1)

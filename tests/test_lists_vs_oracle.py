@@ -161,3 +161,22 @@ def test_schedule_bounds_of_striped_graphs_are_consistent():
             assert max(b["cp"], b["t_seq"] / P) <= b["alap_bound"] + 1e-9
             assert b["alap_bound"] <= b["list_makespan"] + 1e-9
             assert b["list_makespan"] <= b["t_seq"] / P + (1 - 1 / P) * b["cp"] + 1e-9
+
+
+def test_cholinv_graph_matches_oracle():
+    """The library's Cholesky-inversion task graph (steps pipelined) has the
+    oracle's task count and critical paths, in tasks and weighted, for both
+    variants and loop orders (the oracle's graph is pinned to table
+    table:criticalpath)."""
+    from oracle import schedule as S
+    for t in range(1, 12):
+        for variant in (0, 1, 2, 3):
+            inplace, order = not (variant & 1), ("UUU" if variant & 2 else "UDU")
+            nt, cpt, cpw = T.tqr_cholinv_graph_stats(t, variant)
+            du = S.cholinv_dag(t, inplace, order)
+            dw = S.cholinv_dag(t, inplace, order, weights=S.CHOLINV_WEIGHTS)
+            assert nt == len(du.names), (t, variant)
+            assert cpt == S.critical_path(du), (t, variant)
+            assert cpw == S.critical_path(dw), (t, variant)
+    assert T.tqr_cholinv_work_size(1000, 64, 0) > 0 and T.tqr_cholinv_work_size(1000, 48, 0) == 0
+    assert T.tqr_cholinv_work_size(1000, 64, 1) >= 2 * 8 * 1000 * 1000
