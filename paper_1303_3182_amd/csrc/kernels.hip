@@ -1546,8 +1546,9 @@ template <int NB, int IB, int WC>
 __global__ __launch_bounds__(NT, 1) void exec_persistent(ExecArgs a) {
   __shared__ Smem<NB, IB, WC> sm;
   if (a.skip && *a.skip) return;
-  executor_loop(a, &sm.task,
-                [&](const Task &t) { run_task<NB, IB, WC>(a.probs ? a.probs[t.prob] : a.prob, t, sm); });
+  executor_loop(a, &sm.task, [&](const Task &t) __attribute__((always_inline)) {
+    run_task<NB, IB, WC>(a.probs ? a.probs[t.prob] : a.prob, t, sm);
+  });
 }
 
 // Reference executor: one launch runs one task (tasks are launched in a
