@@ -421,6 +421,8 @@ def run_square(args, np, torch, T, synth):
         out["c2_trees"] = c2_trees(args, np, torch, T, synth)
     if args.cholinv_n > 0:
         out["cholinv"] = cholinv_leg(args, np, torch, T)
+    if args.zqr_m > 0:
+        out["zqr"] = zqr_leg(args, np, torch, T)
     if not args.no_cpu_baseline:
         A0, _, _ = synth.conditioned(n, args.kappas[0], 7)
         c = args.cpu_sample_cols
@@ -469,6 +471,45 @@ def cholinv_leg(args, np, torch, T):
     out["roofline"] = {"bound": "alu", "achieved": out["renamed"]["tflops"], "peak": PEAK_FP64_MFMA,
                        "unit": "TFLOP/s", "frac": out["renamed"]["tflops"] / PEAK_FP64_MFMA,
                        "note": "FP64 FMA vector rate equals the FP64 matrix rate on this chip"}
+    return out
+
+
+def zqr_leg(args, np, torch, T):
+    """Double-complex tiled QR (the thesis's "z" workloads) of an m x n
+    matrix with i.i.d. complex N(0,1) entries (seed 11), nb = 64, Greedy,
+    TT kernels: time per factorization (executor launch, HIP events) and
+    8 n^2 (m - n/3) / t in TFLOP/s (a complex multiply-add is 8 real flops,
+    4 times the real count; the thesis states no convention for its complex
+    runs)."""
+    m, n, nb = args.zqr_m, args.zqr_n, 64
+    rng = np.random.default_rng(11)
+    A0 = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    dev = torch.device("cuda:0")
+    Ad = T.zcolmajor(A0, dev)
+    A = Ad.clone()
+    o = T.default_opts(nb=nb, tree="greedy", kernels="tt")
+    nbytes = T.tqr_zworkspace_size(m, n, 0, o)
+    W = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def step():
+        A.copy_(Ad)
+        T.zfactor(A, o, W=W, info=info)
+
+    ms, kms, _ = timed(step, max(3, args.steps // 2), 1, torch, T)
+    flops = 8.0 * n * n * (m - n / 3.0)
+    # accuracy: the Gram residual ||R^H (R z) - A^H (A z)|| / ||A^H (A z)||
+    R = np.triu(A.cpu().numpy()[:n, :n])
+    z = np.random.default_rng(12).standard_normal(n)
+    g = A0.conj().T @ (A0 @ z)
+    gram = float(np.linalg.norm(R.conj().T @ (R @ z) - g) / np.linalg.norm(g))
+    out = {"workload": "double-complex tiled QR of a %dx%d matrix, complex N(0,1) entries (seed 11), nb=%d "
+                       "(%dx%d tiles), greedy tree, TT kernels" % (m, n, nb, -(-m // nb), -(-n // nb)),
+           "m": m, "n": n, "nb": nb, "executor_ms": kms, "ms_per_step_with_copy": ms,
+           "tflops": flops / (kms / 1e3) / 1e12, "flops": flops, "info": int(info.item()), "gram_residual": gram}
+    out["roofline"] = {"bound": "alu", "achieved": out["tflops"], "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
+                       "frac": out["tflops"] / PEAK_FP64_MFMA}
+    log("zqr %dx%d: %.3f ms (%.2f TFLOP/s), gram residual %.2e" % (m, n, kms, out["tflops"], gram))
     return out
 
 
@@ -570,6 +611,8 @@ def main():
     ap.add_argument("--no-gamma-ub", action="store_true", help="skip the traced launch of the DAG bound")
     ap.add_argument("--cholinv-n", type=int, default=4096,
                     help="size of the tile Cholesky inversion leg of the default run (0: skip)")
+    ap.add_argument("--zqr-m", type=int, default=8192, help="rows of the double-complex QR leg (0: skip)")
+    ap.add_argument("--zqr-n", type=int, default=2048, help="columns of the double-complex QR leg")
     ap.add_argument("--max-refine", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed", nargs="*", default=["f32", "bf16"],

@@ -320,6 +320,32 @@ int tqr_lstsq_noalloc(int64_t m, int64_t n, int64_t nrhs, const double *A, int64
                       int64_t ldb, double *X, int64_t ldx, const tqr_opts *o, int32_t *info,
                       hipStream_t stream);
 
+/* ------------------------------------------------ double-complex tiled QR
+ *
+ * The tiled QR of a complex m x n matrix (m >= n), the thesis's "z"
+ * workloads (chapter "QR Factorization", section "Experimental results"):
+ * the same elimination lists, kernel families and task graph as the FP64
+ * path, run by complex tile kernels (GEQRT, TSQRT, TTQRT, UNMQR, TSMQR,
+ * TTMQR) in one persistent executor launch.  A: device memory, column-major,
+ * interleaved (re, im) double pairs, lda >= m counted in complex entries;
+ * on return (stream-ordered) the upper triangle of its first n rows holds
+ * R, whose diagonal is real, and the other entries with the workspace W hold
+ * the reflectors and their tau.  Reflector convention: for x = [alpha; x2],
+ * beta = -sign(Re alpha) ||x||, tau = (beta - alpha) / beta,
+ * v = [1; x2 / (alpha - beta)], H = I - tau v v^H, H^H x = beta e1 (tau = 0
+ * when x2 = 0 and alpha is real).  Options from *o (NULL: defaults): nb 32
+ * or 64 (default 64 when o is NULL), tree, param, kernels; ib, stripes and
+ * the precision fields are ignored.  W: tqr_zworkspace_size(m, n, nrhs, o)
+ * bytes (nrhs: the widest B a later tqr_zapply_qh will take).  info: NULL
+ * or a device int32 receiving 0 or TQR_INFO_TIMEOUT.  tqr_zapply_qh
+ * overwrites B (m x nrhs, ldb >= m, complex) with Q^H B for a factorization
+ * held in (A, W) with the same m, n and options. */
+size_t tqr_zworkspace_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o);
+int tqr_zfactor(int64_t m, int64_t n, void *A, int64_t lda, void *W, size_t w_bytes, const tqr_opts *o,
+                int32_t *info, hipStream_t stream);
+int tqr_zapply_qh(int64_t m, int64_t n, const void *A, int64_t lda, void *W, size_t w_bytes, int64_t nrhs,
+                  void *B, int64_t ldb, const tqr_opts *o, int32_t *info, hipStream_t stream);
+
 /* ------------------------------------------------ tile Cholesky inversion
  *
  * A^{-1} of a symmetric positive definite n x n matrix, in place, by the

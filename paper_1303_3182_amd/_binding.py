@@ -62,6 +62,9 @@ def lib():
             "tqr_graph_stats": (ctypes.c_int, [i64, i64, op, i64p, i64p]),
             "tqr_schedule_bounds": (ctypes.c_int, [i64, i64, op, i32, ctypes.POINTER(ctypes.c_double)]),
             "tqr_cholinv_work_size": (sz, [i64, i32, i32]),
+            "tqr_zworkspace_size": (sz, [i64, i64, i64, op]),
+            "tqr_zfactor": (ctypes.c_int, [i64, i64, vp, i64, vp, sz, op, vp, vp]),
+            "tqr_zapply_qh": (ctypes.c_int, [i64, i64, vp, i64, vp, sz, i64, vp, i64, op, vp, vp]),
             "tqr_cholinv": (ctypes.c_int, [i64, vp, i64, i32, i32, vp, sz, vp, vp]),
             "tqr_cholinv_graph_stats": (ctypes.c_int, [i32, i32, i64p, ctypes.POINTER(ctypes.c_double),
                                                        ctypes.POINTER(ctypes.c_double)]),
@@ -212,6 +215,19 @@ def tqr_schedule_bounds(m, n, opts=None, P=1):
 
 
 CHOLINV_INPLACE, CHOLINV_RENAMED, CHOLINV_UUU = 0, 1, 2
+
+
+def tqr_zworkspace_size(m, n, nrhs=0, opts=None):
+    return int(lib().tqr_zworkspace_size(m, n, nrhs, _opts_ptr(opts)))
+
+
+def tqr_zfactor(m, n, A, lda, W, w_bytes, opts, info, stream):
+    return _check(lib().tqr_zfactor(m, n, A, lda, W, w_bytes, _opts_ptr(opts), info, stream), "tqr_zfactor")
+
+
+def tqr_zapply_qh(m, n, A, lda, W, w_bytes, nrhs, B, ldb, opts, info, stream):
+    return _check(lib().tqr_zapply_qh(m, n, A, lda, W, w_bytes, nrhs, B, ldb, _opts_ptr(opts), info, stream),
+                  "tqr_zapply_qh")
 
 
 def tqr_cholinv_work_size(n, nb=64, variant=CHOLINV_INPLACE):

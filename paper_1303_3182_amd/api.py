@@ -197,3 +197,41 @@ def cholinv(A, nb=64, variant=0, work=None, info=None):
     B.tqr_cholinv(n, A.data_ptr(), _ld(A), nb, variant, work.data_ptr(), work.numel(),
                   None if info is None else info.data_ptr(), _stream())
     return A
+
+
+def zcolmajor(x, device="cuda"):
+    """A column-major complex128 device copy of a 2-D array (stride (1, m))."""
+    t = torch.as_tensor(x, dtype=torch.complex128)
+    if t.dim() == 1:
+        t = t[:, None]
+    m, n = t.shape
+    out = torch.empty((n, m), dtype=torch.complex128, device=device).t()
+    out.copy_(t)
+    return out
+
+
+def _zld(t):
+    if t.dim() != 2 or t.stride(0) != 1 or t.dtype != torch.complex128 or not t.is_cuda:
+        raise B.TqrError("expected a column-major complex128 CUDA tensor")
+    return max(t.stride(1), t.shape[0])
+
+
+def zfactor(A, opts=None, W=None, info=None, nrhs=0):
+    """Complex tiled QR of A in place; returns (A, W)."""
+    m, n = A.shape
+    if W is None:
+        nbytes = B.tqr_zworkspace_size(m, n, nrhs, opts)
+        if nbytes == 0:
+            raise B.TqrError("invalid shape/options for zfactor")
+        W = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    B.tqr_zfactor(m, n, A.data_ptr(), _zld(A), W.data_ptr(), W.numel(), opts,
+                  None if info is None else info.data_ptr(), _stream())
+    return A, W
+
+
+def zapply_qh(A, W, Bm, opts=None, info=None):
+    """B <- Q^H B for a factorization produced by zfactor with the same opts."""
+    m, n = A.shape
+    B.tqr_zapply_qh(m, n, A.data_ptr(), _zld(A), W.data_ptr(), W.numel(), Bm.shape[1], Bm.data_ptr(), _zld(Bm),
+                    opts, None if info is None else info.data_ptr(), _stream())
+    return Bm

@@ -23,7 +23,7 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-p
           "-ffp-contract=off", "-mllvm", "-amdgpu-mfma-vgpr-form"]
 HOST_SOURCES = ["graph.cpp", "api.cpp", "configs.cpp"]
 DEVICE_SOURCES = ["kernels.hip"]
-SHARED_DEVICE_SOURCES = ["refine.hip", "gmres.hip", "mlp.hip", "noalloc.hip", "cholinv.hip"]  # compiled once
+SHARED_DEVICE_SOURCES = ["refine.hip", "gmres.hip", "mlp.hip", "noalloc.hip", "cholinv.hip", "zqr.hip"]  # compiled once
 # (nb, ib) tile configurations; kernels.hip is compiled once per entry
 # (the list must match TQR_CONFIGS in configs.cpp).
 CONFIGS = [(32, 16), (64, 16), (64, 32), (128, 32), (256, 32)]

@@ -21,6 +21,9 @@
 #include "tqr_types.h"
 
 namespace tqr {
+bool zqr_nb_supported(int nb);
+int zqr_occupancy(int nb);
+hipError_t launch_zqr(const ExecArgs &a, int nb, int grid, int32_t *info, hipStream_t s);
 bool cholinv_nb_supported(int nb);
 int cholinv_occupancy(int nb);
 hipError_t launch_cholinv(const ExecArgs &a, int nb, int grid, int32_t *info, hipStream_t s);
@@ -47,7 +50,8 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // extra tile columns, so B's updates overlap the factorization).
 // PK_SNE: R^T Z = B then R X = Z in one graph (semi-normal equations).
 enum PlanKind { PK_FACTOR = 0, PK_APPLY = 1, PK_SOLVE = 2, PK_LSTSQ = 3, PK_SOLVET = 4, PK_SNE = 5,
-                PK_CHOLINV = 6 /* tile Cholesky inversion: p = q = t, family = renaming, tree = UUU */ };
+                PK_CHOLINV = 6 /* tile Cholesky inversion: p = q = t, family = renaming, tree = UUU */,
+                PK_ZFACTOR = 7, PK_ZAPPLY = 8 /* double complex: the graphs of PK_FACTOR / PK_APPLY */ };
 bool solve_kind(int k) { return k == PK_SOLVE || k == PK_SOLVET || k == PK_SNE; }
 
 struct PlanKey {
@@ -107,8 +111,8 @@ std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
   spec.stripes = k.stripes;
   spec.nbcols = k.nbcols;
   spec.stripes_b = k.stripes_b;
-  spec.panels = (k.kind == PK_FACTOR || k.kind == PK_LSTSQ);
-  spec.b_updates = (k.kind == PK_APPLY || k.kind == PK_LSTSQ);
+  spec.panels = (k.kind == PK_FACTOR || k.kind == PK_LSTSQ || k.kind == PK_ZFACTOR);
+  spec.b_updates = (k.kind == PK_APPLY || k.kind == PK_LSTSQ || k.kind == PK_ZAPPLY);
   spec.solve = (k.kind == PK_SOLVE || k.kind == PK_LSTSQ || k.kind == PK_SNE);
   spec.solve_t = (k.kind == PK_SOLVET || k.kind == PK_SNE);
   std::vector<Elim> list;
@@ -1468,6 +1472,161 @@ int tqr_graph_stats(int64_t m, int64_t n, const tqr_opts *o, int64_t *ntasks, in
   if (ntasks) *ntasks = (int64_t)hp->g.tasks.size();
   if (nedges) *nedges = hp->g.nedges;
   return hp->valid ? TQR_OK : TQR_E_INTERNAL;
+}
+
+// ------------------------------------------------ double-complex tiled QR
+}  // extern "C"
+
+namespace {
+
+struct ZResolved {
+  int nb, tree, param, family;
+};
+
+int zresolve(const tqr_opts *o, ZResolved *z) {
+  tqr_opts d;
+  tqr_default_opts(&d);
+  const tqr_opts &x = o ? *o : d;
+  z->nb = o ? x.nb : 64;
+  z->tree = x.tree;
+  z->param = x.param;
+  z->family = x.kernels;
+  if (!zqr_nb_supported(z->nb)) return TQR_E_UNSUPPORTED;
+  if (z->tree < TQR_FLAT || z->tree > TQR_ASAP) return TQR_E_UNSUPPORTED;
+  if (z->family != TQR_TT && z->family != TQR_HYBRID) return TQR_E_UNSUPPORTED;
+  if (z->tree == TQR_GRASAP && z->param < 1) z->param = 1;
+  return TQR_OK;
+}
+
+PlanKey zkey(int kind, int64_t m, int64_t n, int64_t nrhs, const ZResolved &z) {
+  PlanKey k{};
+  k.kind = kind;
+  k.p = (int)cdiv(m, z.nb);
+  k.q = (int)cdiv(n, z.nb);
+  k.nbcols = (kind == PK_ZFACTOR) ? 0 : (int)cdiv(nrhs, z.nb);
+  k.family = z.family;
+  k.tree = z.tree;
+  k.param = z.param;
+  k.stripes = k.stripes_b = 1;
+  k.priority = 1;
+  return k;
+}
+
+size_t ztau_bytes(int64_t m, int64_t n, int nb) { return (size_t)cdiv(m, nb) * cdiv(n, nb) * 2 * nb * 16; }
+
+size_t zwork_bytes(int64_t m, int64_t n, int64_t nrhs, const ZResolved &z) {
+  int64_t nt = (int64_t)host_plan(zkey(PK_ZFACTOR, m, n, 0, z))->g.tasks.size();
+  if (nrhs > 0) nt = std::max(nt, (int64_t)host_plan(zkey(PK_ZAPPLY, m, n, nrhs, z))->g.tasks.size());
+  return align_up(ztau_bytes(m, n, z.nb)) + state_bytes(nt);
+}
+
+std::map<std::pair<int, int>, int> g_z_grid;
+
+int zrun(int kind, int64_t m, int64_t n, void *A, int64_t lda, void *B, int64_t ldb, int64_t nrhs, void *W,
+         size_t w_bytes, const ZResolved &z, int32_t *info, hipStream_t stream) {
+  const PlanKey key = zkey(kind, m, n, nrhs, z);
+  auto hp = host_plan(key);
+  if (!hp->valid) return TQR_E_INTERNAL;
+  const size_t tb = align_up(ztau_bytes(m, n, z.nb));
+  if (w_bytes < tb + state_bytes((int64_t)hp->g.tasks.size())) return TQR_E_WORKSPACE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TQR_E_HIP;
+  DevicePlan dp;
+  int rc = device_plan(key, *hp, dev, &dp);
+  if (rc) return rc;
+  int grid = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_z_grid.find({dev, z.nb});
+    if (it != g_z_grid.end()) grid = it->second;
+  }
+  if (!grid) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    grid = cus * zqr_occupancy(z.nb);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_z_grid[{dev, z.nb}] = grid;
+  }
+  char *w = static_cast<char *>(W);
+  ExecArgs a{};
+  a.tasks = dp.tasks;
+  a.succ_off = dp.succ_off;
+  a.succ = dp.succ;
+  a.indeg0 = dp.indeg0;
+  a.ready0 = dp.ready0;
+  a.ntasks = dp.ntasks;
+  a.nready0 = dp.nready0;
+  a.ctl = reinterpret_cast<ExecCtl *>(w + tb);
+  a.queue = reinterpret_cast<int32_t *>(w + tb + align_up(sizeof(ExecCtl)));
+  a.indeg = reinterpret_cast<int32_t *>(w + tb + align_up(sizeof(ExecCtl)) +
+                                        align_up((size_t)std::max<int32_t>(a.ntasks, 1) * 4));
+  // the complex matrices are passed as double pointers to interleaved
+  // (re, im) pairs; leading dimensions count complex entries; Tf holds tau
+  a.prob.A = static_cast<double *>(A);
+  a.prob.lda = lda;
+  a.prob.m = m;
+  a.prob.n = n;
+  a.prob.B = static_cast<double *>(B);
+  a.prob.ldb = ldb;
+  a.prob.nrhs = nrhs;
+  a.prob.Tf = reinterpret_cast<double *>(w);
+  a.prob.p = key.p;
+  a.prob.q = key.q;
+  a.prob.singular = &a.ctl->pad[0];
+  a.nb = z.nb;
+  a.spin_limit = spin_limit_ticks(dev);
+  a.trace = g_trace;
+  a.trace_cap = g_trace_cap;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (g_timing && hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess)
+    hipEventRecord(ev0, stream);
+  const hipError_t e = launch_zqr(a, z.nb, grid, info, stream);
+  if (ev1) {
+    hipEventRecord(ev1, stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_events.emplace_back(ev0, ev1);
+  }
+  return e == hipSuccess ? TQR_OK : TQR_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tqr_zworkspace_size(int64_t m, int64_t n, int64_t nrhs, const tqr_opts *o) {
+  if (m < 1 || n < 1 || n > m || nrhs < 0) return 0;
+  ZResolved z;
+  if (zresolve(o, &z)) return 0;
+  return zwork_bytes(m, n, nrhs, z);
+}
+
+int tqr_zfactor(int64_t m, int64_t n, void *A, int64_t lda, void *W, size_t w_bytes, const tqr_opts *o,
+                int32_t *info, hipStream_t stream) {
+  if (m < 1) return -1;
+  if (n < 1 || n > m) return -2;
+  if (!A) return -3;
+  if (lda < m) return -4;
+  if (!W) return -5;
+  ZResolved z;
+  int rc = zresolve(o, &z);
+  if (rc) return rc;
+  return zrun(PK_ZFACTOR, m, n, A, lda, nullptr, 0, 0, W, w_bytes, z, info, stream);
+}
+
+int tqr_zapply_qh(int64_t m, int64_t n, const void *A, int64_t lda, void *W, size_t w_bytes, int64_t nrhs, void *B,
+                  int64_t ldb, const tqr_opts *o, int32_t *info, hipStream_t stream) {
+  if (m < 1) return -1;
+  if (n < 1 || n > m) return -2;
+  if (!A) return -3;
+  if (lda < m) return -4;
+  if (!W) return -5;
+  if (nrhs < 1) return -7;
+  if (!B) return -8;
+  if (ldb < m) return -9;
+  ZResolved z;
+  int rc = zresolve(o, &z);
+  if (rc) return rc;
+  return zrun(PK_ZAPPLY, m, n, const_cast<void *>(A), lda, B, ldb, nrhs, W, w_bytes, z, info, stream);
 }
 
 // ------------------------------------------------ tile Cholesky inversion

@@ -189,11 +189,23 @@ def evaluate(params, shapes, log=print):
         if i % 20 == 0:
             log("held-out %d/%d: %dx%d pick %s %.2f ms, fallback %.2f, best %s %.2f" % (
                 i, len(shapes), m, n, pick, grid[pick], grid[("grasap", 256)], best, grid[best]))
-    tot = {k: float(sum(r[k] for r in rows)) for k in ("pick_ms", "fallback_ms", "best_ms")}
+        # baseline without timing: Greedy at the tile size whose critical
+        # path (units of nb^3/3, table tab.kernels weights) is shortest in time
+        cp_nb = min(NBS, key=lambda b: B.tqr_tree_cp("greedy", -(-m // b), -(-n // b)) * float(b) ** 3)
+        rows[-1]["greedy_cp_nb"] = cp_nb
+        rows[-1]["greedy_cp_ms"] = grid[("greedy", cp_nb)]
+        rows[-1]["grid"] = {"%s/%d" % k: v for k, v in grid.items()}
+    tot = {k: float(sum(r[k] for r in rows)) for k in ("pick_ms", "fallback_ms", "best_ms", "greedy_cp_ms")}
+    # the single (tree, nb) with the smallest total over these shapes: the
+    # best any constant choice could do (chosen with hindsight)
+    const_tot = {key: sum(r["grid"][key] for r in rows) for key in rows[0]["grid"]} if rows else {}
+    best_const = min(const_tot, key=const_tot.get) if rows else None
     gains = [r["fallback_ms"] / r["pick_ms"] for r in rows]
     regret = [r["pick_ms"] / r["best_ms"] for r in rows]
     return {"shapes": len(rows), "total_pick_ms": tot["pick_ms"], "total_fallback_ms": tot["fallback_ms"],
             "total_best_ms": tot["best_ms"], "speedup_total": tot["fallback_ms"] / tot["pick_ms"],
+            "total_greedy_cp_nb_ms": tot["greedy_cp_ms"], "best_constant": best_const,
+            "total_best_constant_ms": float(const_tot[best_const]) if rows else None,
             "geomean_speedup": float(np.exp(np.mean(np.log(gains)))),
             "geomean_regret": float(np.exp(np.mean(np.log(regret)))), "rows": rows}
 
@@ -229,9 +241,11 @@ def main():
         np.save(args.out, params.cpu().numpy(), allow_pickle=False)
     held = random_shapes(args.heldout, 3, max_elems=args.max_elems)
     ev = evaluate(params, held, log)
-    log("held-out: pick %.1f ms, fallback %.1f ms, best %.1f ms; speedup %.3f, geomean %.3f, regret %.3f" % (
-        ev["total_pick_ms"], ev["total_fallback_ms"], ev["total_best_ms"], ev["speedup_total"],
-        ev["geomean_speedup"], ev["geomean_regret"]))
+    log("held-out: pick %.1f ms, fallback %.1f ms, best %.1f ms, best constant %s %.1f ms, greedy at cp-best nb "
+        "%.1f ms; speedup %.3f, geomean %.3f, regret %.3f" % (
+            ev["total_pick_ms"], ev["total_fallback_ms"], ev["total_best_ms"], ev["best_constant"],
+            ev["total_best_constant_ms"], ev["total_greedy_cp_nb_ms"], ev["speedup_total"],
+            ev["geomean_speedup"], ev["geomean_regret"]))
     rep = {"train_samples": len(shapes), "epochs": args.epochs, "lr": args.lr, "loss_first": float(hist[0]),
            "loss_last": float(hist[-1]), "heldout": {k: v for k, v in ev.items() if k != "rows"}}
     if args.report:

@@ -104,10 +104,10 @@ def test_auto_without_network_is_grasap_256_and_with_one_a_candidate():
 @pytest.mark.skipif(not os.path.exists(S.WEIGHTS), reason="no trained selector weights shipped")
 def test_trained_selector_gain_over_fallback():
     """The shipped network (trained on engine timings) against GrASAP at
-    nb = 256 on shapes it was not trained on: total measured time of its
-    picks is not above the fallback's (and is reported)."""
+    nb = 256 on shapes it was not trained on: the total measured time of its
+    picks is below the fallback's (the ratio is reported)."""
     p = S.load_selector()
-    shapes = S.random_shapes(8, 99, max_elems=1 << 23)
+    shapes = S.random_shapes(8, 99, max_elems=1 << 25)
     pick_ms = fall_ms = 0.0
     for i, (m, n) in enumerate(shapes):
         tid, nb, ib = S.select(m, n)
@@ -119,5 +119,5 @@ def test_trained_selector_gain_over_fallback():
         fall_ms += f
     print("selector gain over GrASAP@256 on %d held-out shapes: %.3fx" % (len(shapes), fall_ms / pick_ms))
     S.set_selector(None)
-    assert pick_ms <= 1.05 * fall_ms
+    assert pick_ms < fall_ms
     assert p is not None
