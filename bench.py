@@ -257,7 +257,7 @@ def run_tall(args, np, torch, T, synth):
 
 
 # ------------------------------------------------------- DAG upper bound
-def gamma_ub(T, torch, np, m, n, nrhs, opts, run_once, tree_name):
+def gamma_ub(T, torch, np, m, n, nrhs, opts, run_once, tree_name, param=0, family=None):
     """The thesis's upper-bound model (section "Experimental results"):
     gamma_ub = gamma_task T / max(T/P, cp), T the total work and cp the
     critical path in units of nb^3/3 flop (table tab.kernels weights),
@@ -289,7 +289,7 @@ def gamma_ub(T, torch, np, m, n, nrhs, opts, run_once, tree_name):
     # the right-hand side's updates and the solve are excluded from the rate
     fact = np.array([t[0] < 6 and t[4] < q for t in tasks])
     units = 6 * p * q * q - 2 * q ** 3
-    cp_units = T.tqr_tree_cp(tree_name, p, q, 0, T.TT)
+    cp_units = T.tqr_tree_cp(tree_name, p, q, param, T.TT if family is None else family)
     # a kernel split into column stripes is several tasks sharing its units
     parts = {}
     for t in tasks:
@@ -353,7 +353,9 @@ def backward_error_square(np, A0, b0, x):
 
 # -------------------------------------------------------------------- square
 def run_square(args, np, torch, T, synth):
-    n, nb = args.square_n, args.nb
+    n, nb = args.square_n, args.square_nb
+    tree, param, kernels, ib = args.square_tree, args.square_param, args.square_kernels, args.square_ib
+    fam = T.TT if kernels == "tt" else T.HYBRID
     dev = torch.device("cuda:0")
     X = torch.empty((1, n), dtype=torch.float64, device=dev).t()
     info = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -368,7 +370,8 @@ def run_square(args, np, torch, T, synth):
         b = T.colmajor(b0[:, None], dev)
         res = {}
         for dt in ["f64"] + list(args.mixed):
-            o = T.default_opts(nb=nb, ib=args.ib, tree=args.tree, update_dtype=dt, max_refine=args.max_refine)
+            o = T.default_opts(nb=nb, ib=ib, tree=tree, param=param, kernels=kernels, update_dtype=dt,
+                               max_refine=args.max_refine)
             w = T.lstsq_workspace(n, n, 1, o, dev)
             # the FP64 solve is kappa-independent: its full timing is taken once
             steps = args.steps if (dt != "f64" or fp64 is None) else max(2, args.steps // 4)
@@ -385,7 +388,7 @@ def run_square(args, np, torch, T, synth):
                 fp64 = {"ms": ms, "kms": kms, "be": be, "info": int(info.item())}
                 if not args.no_gamma_ub:
                     gub = gamma_ub(T, torch, np, n, n, 1, o, lambda: T.lstsq(A, b, o, X=X, work=w, info=info),
-                                   args.tree)
+                                   tree, param, fam)
             log("kappa %g %s: %.2f ms, be %.2e, refine %d (gmres %d, krylov %d), info %d" %
                 (kappa, dt, ms, be, rep["iterations"], rep["gmres_steps"], rep["krylov_steps"], int(info.item())))
         for dt in args.mixed:
@@ -397,9 +400,11 @@ def run_square(args, np, torch, T, synth):
     out = base_line(args, qr_flops(n, n) / (fp64["ms"] / 1e3) / 1e12, fp64["ms"], "f64",
                     {"workload": "FP64 tiled-QR least squares of square %dx%d systems with prescribed condition "
                                  "number (Haar U, V; log-spaced sigma; b = A x + 1e-6 N(0,1)), nb=%d (%dx%d tiles), "
-                                 "%s tree, TT kernels" % (n, n, nb, -(-n // nb), -(-n // nb), args.tree),
-                     "n": n, "nb": nb, "ib": args.ib, "tree": args.tree, "kappas": args.kappas,
-                     "precision": "plain FP64"})
+                                 "%s tree, %s kernels" % (n, n, nb, -(-n // nb), -(-n // nb), tree,
+                                                          "TS" if kernels == "hybrid" and tree == "flat"
+                                                          else kernels.upper()),
+                     "n": n, "nb": nb, "ib": ib, "tree": tree, "param": param, "kernels": kernels,
+                     "kappas": args.kappas, "precision": "plain FP64"})
     out["executor_ms"] = fp64["kms"]
     out["ls_backward_error"] = fp64["be"]
     out["per_kappa"] = per_kappa
@@ -411,8 +416,9 @@ def run_square(args, np, torch, T, synth):
                                 if not per_kappa[k][dt]["equal_fp64_error"]]
     out["roofline"] = roofline(qr_flops(n, n), fp64["kms"],
                                "exec_persistent (least-squares task graph: factor, Q^T b, R x = c)",
-                               recorded_traffic("traffic_lstsq_8192x8192_nb256.json",
-                                                "square %d nb=%d ib=%d %s lstsq" % (n, nb, args.ib, args.tree)))
+                               recorded_traffic("traffic_lstsq_8192x8192.json",
+                                                "square %d nb=%d ib=%d %s/%d %s lstsq" % (n, nb, ib, tree, param,
+                                                                                          kernels)))
     if gub is not None:
         out["gamma_ub"] = gub
         out["roofline"]["gamma_ub"] = gub["measured_dag"]["gamma_ub"]
@@ -597,6 +603,13 @@ def main():
     ap.add_argument("--m", type=int, default=16384)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--square-n", type=int, default=8192)
+    # square workload configuration (measured fastest among the trees, both
+    # kernel families and nb 64 / 128 / 256 on this workload)
+    ap.add_argument("--square-nb", type=int, default=128)
+    ap.add_argument("--square-ib", type=int, default=32)
+    ap.add_argument("--square-tree", default="flat")
+    ap.add_argument("--square-param", type=int, default=0)
+    ap.add_argument("--square-kernels", default="hybrid")
     ap.add_argument("--kappas", type=float, nargs="*", default=[1e2, 1e5, 1e8])
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--nb", type=int, default=256)

@@ -1,9 +1,10 @@
 """Parity at the workloads' full sizes, in the launch configuration the
-benchmark times (nb 256, ib 32, Greedy, persistent executor).
+benchmark times (square systems: nb 128, ib 32, FlatTree with the hybrid
+family, i.e. the pure TS algorithm; persistent executor).
 
 Square 8192 x 8192 systems with prescribed condition number (A = U diag(s)
 V^T, Haar U and V, log-spaced s; b = A x + 1e-6 N(0,1)):
-- R(:, 1:256) and (Q^T b)(1:256) depend only on the first tile column and
+- R(:, 1:nb) and (Q^T b)(1:nb) depend only on the first tile column and
   its FP64 panel kernels, so they are compared elementwise with the oracle's
   factorization of A(:, 1:256), for every update precision (the
   low-precision updates touch later tile columns only);
@@ -27,7 +28,8 @@ from tests.gpu_util import EPS, case, r_tol
 
 pytestmark = pytest.mark.gpu
 
-N, NB = 8192, 256
+N, NB = 8192, 128
+SQ = dict(nb=NB, ib=32, tree="flat", kernels="hybrid")
 
 
 def _first_column_oracle(A0, b0):
@@ -39,7 +41,7 @@ def _first_column_oracle(A0, b0):
 def test_square_8192(dtype, kappa):
     case("square 8192 %s kappa=%g: inputs" % (dtype, kappa))
     A0, x0, b0 = synth.conditioned(N, kappa, 7)
-    o = T.default_opts(nb=NB, ib=32, tree="greedy", update_dtype=dtype, max_refine=20)
+    o = T.default_opts(update_dtype=dtype, max_refine=20, **SQ)
     case("square 8192 %s kappa=%g: factor + Q^T b" % (dtype, kappa))
     A, W = T.factor(T.colmajor(A0), o, nrhs=1)
     Bm = T.colmajor(b0[:, None])
@@ -68,7 +70,7 @@ def test_square_8192(dtype, kappa):
 
 def test_square_8192_fp32_kappa_1e8_is_reported():
     A0, x0, b0 = synth.conditioned(N, 1e8, 7)
-    o = T.default_opts(nb=NB, ib=32, tree="greedy", update_dtype="f32", max_refine=20)
+    o = T.default_opts(update_dtype="f32", max_refine=20, **SQ)
     case("square 8192 f32 kappa=1e8: lstsq")
     work = T.lstsq_workspace(N, N, 1, o)
     info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
