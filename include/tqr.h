@@ -85,11 +85,25 @@ typedef struct tqr_opts {
   int32_t exec;         /* enum tqr_exec (default persistent)               */
   int32_t stripes;      /* update tasks per tile (0: 1 up to nb 128, 4 at 256) */
   int32_t max_refine;   /* refinement steps for mixed precision (def. 10)   */
-  int32_t priority;     /* 1 = critical-path-first ready order (default 1)  */
+  int32_t priority;     /* enum tqr_priority (default TQR_PRIO_STATIC)      */
   int32_t refine_method;/* enum tqr_refine (default TQR_REFINE_AUTO)        */
   int32_t reserved;     /* 0                                                */
   double refine_tol;    /* refinement stop, relative backward error (0=auto)*/
 } tqr_opts;
+
+/* Order in which the executor starts ready tasks (one persistent launch
+ * runs a task graph; thesis section "Execution schemes" leaves the order
+ * to the runtime):
+ *   TQR_PRIO_LIST    one FIFO ready queue, successors in list order;
+ *   TQR_PRIO_BOTTOM  one FIFO ready queue, successors and the initially
+ *                    ready tasks by decreasing bottom level (longest path
+ *                    to the end, tab.kernels weights);
+ *   TQR_PRIO_STATIC  (default) the queue filled once, in the start order of
+ *                    a critical-path list schedule of the graph simulated
+ *                    on the executor's workgroups with estimated GPU task
+ *                    durations; workgroups take the tasks in that order,
+ *                    each waiting only for its task's predecessors. */
+enum tqr_priority { TQR_PRIO_LIST = 0, TQR_PRIO_BOTTOM = 1, TQR_PRIO_STATIC = 2 };
 
 /* Refinement after low-precision updates (tqr_lstsq, one problem):
  * AUTO takes classical steps and, for a square system with one right-hand
@@ -448,6 +462,13 @@ int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_
  * number of edges, or a negative value (bad arguments, cap too small). */
 int tqr_debug_succ(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *off,
                    int32_t *succ, int64_t cap);
+
+/* Debug only: the initially ready tasks of a plan (kind and nrhs as for
+ * tqr_debug_graph) in queue order: with TQR_PRIO_STATIC every task, in the
+ * order the executor hands them out.  Returns their number, or a negative
+ * value (bad arguments, cap too small). */
+int tqr_debug_ready(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *ready,
+                    int64_t cap);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,7 @@ TT, HYBRID = 0, 1
 F64, F32, BF16 = 0, 1, 2
 EXEC_PERSISTENT, EXEC_SEQUENTIAL = 0, 1
 REFINE_AUTO, REFINE_CLASSICAL, REFINE_GMRES = 0, 1, 2
+PRIO_LIST, PRIO_BOTTOM, PRIO_STATIC = 0, 1, 2
 
 
 class TqrError(RuntimeError):
@@ -92,6 +93,7 @@ def lib():
             "tqr_debug_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), i64p]),
             "tqr_debug_graph": (ctypes.c_int, [i64, i64, i64, i32, op, i32p, i64]),
             "tqr_debug_succ": (ctypes.c_int, [i64, i64, i64, i32, op, i32p, i32p, i64]),
+            "tqr_debug_ready": (ctypes.c_int, [i64, i64, i64, i32, op, i32p, i64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -127,6 +129,8 @@ def default_opts(**kw):
             v = {"f64": F64, "f32": F32, "bf16": BF16}[v]
         if k == "refine_method" and isinstance(v, str):
             v = {"auto": REFINE_AUTO, "classical": REFINE_CLASSICAL, "gmres": REFINE_GMRES}[v]
+        if k == "priority" and isinstance(v, str):
+            v = {"list": PRIO_LIST, "bottom": PRIO_BOTTOM, "static": PRIO_STATIC}[v]
         setattr(o, k, v)
     return o
 
@@ -298,6 +302,18 @@ def debug_graph(m, n, opts=None, nrhs=0, kind=0):
     buf = (ctypes.c_int32 * (8 * max(nt, 1)))()
     L.tqr_debug_graph(m, n, nrhs, kind, _opts_ptr(opts), buf, nt)
     return [tuple(buf[8 * t:8 * t + 8]) for t in range(nt)]
+
+
+def debug_ready(m, n, opts=None, nrhs=0, kind=0):
+    """Initially ready tasks of a plan in queue order (with the static order:
+    every task, in the order the executor hands them out)."""
+    L = lib()
+    nt = len(debug_graph(m, n, opts, nrhs, kind))
+    ready = (ctypes.c_int32 * max(nt, 1))()
+    nr = L.tqr_debug_ready(m, n, nrhs, kind, _opts_ptr(opts), ready, nt)
+    if nr < 0:
+        raise TqrError("tqr_debug_ready failed (%d)" % nr)
+    return list(ready[:nr])
 
 
 def debug_succ(m, n, opts=None, nrhs=0, kind=0):

@@ -56,10 +56,11 @@ bool solve_kind(int k) { return k == PK_SOLVE || k == PK_SOLVET || k == PK_SNE; 
 
 struct PlanKey {
   int kind, p, q, nbcols, family, tree, param, stripes, stripes_b, priority;
+  int nb, P;  // tile size and executor workgroups, for the static order only (else 0)
   bool operator<(const PlanKey &o) const {
-    return std::tie(kind, p, q, nbcols, family, tree, param, stripes, stripes_b, priority) <
+    return std::tie(kind, p, q, nbcols, family, tree, param, stripes, stripes_b, priority, nb, P) <
            std::tie(o.kind, o.p, o.q, o.nbcols, o.family, o.tree, o.param, o.stripes, o.stripes_b,
-                    o.priority);
+                    o.priority, o.nb, o.P);
   }
 };
 
@@ -72,6 +73,7 @@ struct DevicePlan {
   Task *tasks = nullptr;
   int32_t *succ_off = nullptr, *succ = nullptr, *indeg0 = nullptr, *ready0 = nullptr;
   int32_t ntasks = 0, nready0 = 0;
+  int32_t static_order = 0;        // ready0 is a precomputed order of every task
 };
 
 std::mutex g_mu;
@@ -119,6 +121,8 @@ std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
   if (!solve_kind(k.kind)) list = make_list(k.tree, k.p, k.q, k.param);
   hp->g = build_graph(list, spec);
   finalize(hp->g, k.priority != 0);
+  if (k.priority == TQR_PRIO_STATIC && k.kind != PK_ZFACTOR && k.kind != PK_ZAPPLY)
+    static_list_order(hp->g, k.P, k.nb);
   hp->valid = validate(hp->g);
   // the host structure is only needed for sequential order and statistics
   hp->g.preds.clear();
@@ -155,6 +159,7 @@ int device_plan(const PlanKey &k, const HostPlan &hp, int dev, DevicePlan *out) 
     return TQR_E_NOMEM;
   d.ntasks = (int32_t)g.tasks.size();
   d.nready0 = (int32_t)g.ready0.size();
+  d.static_order = g.static_order ? 1 : 0;
   g_dev[key] = d;
   *out = d;
   return TQR_OK;
@@ -171,6 +176,14 @@ int grid_size(int dev, int nb, int ib) {
   const int grid = cus * std::max(1, occ);
   g_grid[dev * 1024 + nb * 4 + ib / 16] = grid;
   return grid;
+}
+
+// Executor workgroups on the current device, the P of the static list
+// order (256, one per CU of MI355X at nb >= 128, when no device is visible).
+int current_grid(int nb, int ib) {
+  int count = 0, dev = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1 || hipGetDevice(&dev) != hipSuccess) return 256;
+  return grid_size(dev, nb, ib);
 }
 
 int64_t g_spin_override = 0;  // tqr_debug_spin_limit; 0 = the default below
@@ -292,6 +305,7 @@ int resolve(const tqr_opts *o, Resolved *r, int64_t m = 0, int64_t n = 0) {
   if (r->tree < TQR_FLAT || r->tree > TQR_ASAP) return TQR_E_UNSUPPORTED;
   if (r->family != TQR_TT && r->family != TQR_HYBRID) return TQR_E_UNSUPPORTED;
   if (r->exec != TQR_EXEC_PERSISTENT && r->exec != TQR_EXEC_SEQUENTIAL) return TQR_E_UNSUPPORTED;
+  if (r->priority < TQR_PRIO_LIST || r->priority > TQR_PRIO_STATIC) return TQR_E_UNSUPPORTED;
   if (x.update_dtype != TQR_F64 && x.update_dtype != TQR_F32 && x.update_dtype != TQR_BF16)
     return TQR_E_UNSUPPORTED;
   r->update_dtype = x.update_dtype;
@@ -325,6 +339,8 @@ PlanKey make_key(int kind, int p, int q, int64_t nrhs, const Resolved &r) {
   // right-hand sides narrower than one stripe get one task per tile
   k.stripes_b = (kind == PK_FACTOR || nrhs <= r.nb / r.stripes) ? 1 : r.stripes;
   k.priority = r.priority;
+  k.nb = (r.priority == TQR_PRIO_STATIC) ? r.nb : 0;
+  k.P = (r.priority == TQR_PRIO_STATIC) ? current_grid(r.nb, r.ib) : 0;
   if (solve_kind(kind)) k.family = 0;
   return k;
 }
@@ -368,6 +384,7 @@ int run_plan(int kind, int64_t m, int64_t n, double *A, int64_t lda, double *B, 
   a.ready0 = dp.ready0;
   a.ntasks = dp.ntasks;
   a.nready0 = dp.nready0;
+  a.static_order = dp.static_order;
   char *st = base + kHeader + align_up(tf);
   a.ctl = reinterpret_cast<ExecCtl *>(st);
   a.queue = reinterpret_cast<int32_t *>(st + align_up(sizeof(ExecCtl)));
@@ -528,7 +545,9 @@ BatchKey batch_key(int kind, int count, const int64_t *m, const int64_t *n, int6
   k.ib = r.ib;
   k.family = solve_kind(kind) ? 0 : r.family;
   k.stripes = r.stripes;
-  k.priority = r.priority;
+  // the concatenated graph is pushed dynamically: its parts keep their
+  // initially ready tasks (no static order)
+  k.priority = std::min(r.priority, (int)TQR_PRIO_BOTTOM);
   k.nrhs = nrhs;
   k.shape.reserve((size_t)count * 4);
   for (int x = 0; x < count; x++) {
@@ -560,6 +579,7 @@ std::shared_ptr<BatchPlan> batch_plan(const BatchKey &k, const Resolved &r, int 
   bool valid = true;
   for (int x = 0; x < count; x++) {
     Resolved rx = r;
+    rx.priority = k.priority;
     rx.tree = k.shape[4 * x + 2];
     rx.param = k.shape[4 * x + 3];
     auto hp = host_plan(make_key(k.kind, k.shape[4 * x], k.shape[4 * x + 1], k.kind == PK_FACTOR ? 0 : k.nrhs, rx));
@@ -745,7 +765,7 @@ void tqr_default_opts(tqr_opts *o) {
   o->exec = TQR_EXEC_PERSISTENT;
   o->stripes = 0;
   o->max_refine = 10;
-  o->priority = 1;
+  o->priority = TQR_PRIO_STATIC;
   o->refine_method = TQR_REFINE_AUTO;
   o->refine_tol = 0.0;
 }
@@ -892,6 +912,7 @@ int place_plan(const Graph &g, char *dst, hipStream_t stream, DevicePlan *out) {
   out->ready0 = r0;
   out->ntasks = (int32_t)g.tasks.size();
   out->nready0 = (int32_t)g.ready0.size();
+  out->static_order = g.static_order ? 1 : 0;
   return TQR_OK;
 }
 
@@ -1877,6 +1898,20 @@ int tqr_debug_succ(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_o
   std::copy(hp->g.succ_off.begin(), hp->g.succ_off.end(), off);
   std::copy(hp->g.succ.begin(), hp->g.succ.end(), succ);
   return (int)hp->g.succ.size();
+}
+
+int tqr_debug_ready(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *ready,
+                    int64_t cap) {
+  if (m < 1 || n < 1 || n > m) return -1;
+  if (kind < PK_FACTOR || kind > PK_SNE) return -4;
+  Resolved r;
+  int rc = resolve(o, &r, m, n);
+  if (rc) return rc;
+  auto hp = host_plan(make_key(kind, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), kind == PK_FACTOR ? 0 : nrhs, r));
+  const Graph &g = hp->g;
+  if ((int64_t)g.ready0.size() > cap) return -1;
+  std::copy(g.ready0.begin(), g.ready0.end(), ready);
+  return (int)g.ready0.size();
 }
 
 const char *tqr_strerror(int code) {

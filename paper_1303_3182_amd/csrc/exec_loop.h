@@ -49,11 +49,14 @@ __device__ __forceinline__ void executor_reset(const ExecArgs &a) {
 }
 
 // The persistent loop: every workgroup pops queue slots in order, waits for
-// the slot to be filled, runs the task (run(task), every thread of the
-// workgroup), then releases its successors; a successor whose count reaches
-// zero is pushed.  Every task is pushed exactly once, so a workgroup that
-// pops slot h >= ntasks exits.  A spin that exceeds spin_limit sets
-// abort/error and every workgroup exits.  Memory ordering costs whole-L2
+// the slot to be filled and its task's predecessors to be finished, runs
+// the task (run(task), every thread of the workgroup), then releases its
+// successors; a successor whose count reaches zero is pushed, unless the
+// reset filled the whole queue with a precomputed order (static_order,
+// where every task follows all its predecessors, so the earliest unfinished
+// slot can always start).  Every task is in the queue exactly once, so a
+// workgroup that pops slot h >= ntasks exits.  A spin that exceeds
+// spin_limit sets abort/error and every workgroup exits.  Memory ordering costs whole-L2
 // operations on this chip (an agent-scope release writes back the XCD's
 // L2, an acquire invalidates it), so each task pays exactly one of each: no
 // acquire while polling, none on push.  `slot` is an int in LDS.
@@ -117,7 +120,8 @@ __device__ __forceinline__ void executor_loop(const ExecArgs &a, int *slot, Run 
       }
       for (int e = a.succ_off[tid]; e < a.succ_off[tid + 1]; e++) {
         const int s = a.succ[e];
-        if (__hip_atomic_fetch_add(&a.indeg[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+        if (__hip_atomic_fetch_add(&a.indeg[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1 &&
+            !a.static_order) {
           const int q = __hip_atomic_fetch_add(&ctl->tail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_store(&a.queue[q], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }

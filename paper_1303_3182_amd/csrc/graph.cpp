@@ -426,6 +426,83 @@ void finalize(Graph &g, bool priority) {
   for (int t = 0; t < n; t++) g.order[t] = t;
 }
 
+namespace {
+// Estimated GPU duration per unit of tab.kernels weight (arbitrary time
+// unit), from per-task traces on MI355X at nb 128 (GEQRT 148 us, TSQRT
+// 185, UNMQR 51, TSMQR 72, TRSM 20, GEMM 10 with one right-hand side) and
+// nb 256 (TTQRT 2.2 x, TTMQR 1.2 x GEQRT's / UNMQR's time per unit).
+// Panel kernels scale with 128 / nb per unit.
+double gpu_cost_per_unit(int kind, int nb) {
+  const double panel = 128.0 / (double)nb;
+  switch (kind) {
+    case K_GEQRT: return 37.0 * panel;
+    case K_TSQRT: return 31.0 * panel;
+    case K_TTQRT: return 69.0 * panel;
+    case K_UNMQR: return 8.5;
+    case K_TSMQR: return 6.0;
+    case K_TTMQR: return 10.0;
+    case K_TRSM:
+    case K_TRSMT: return 20.0;
+    case K_GEMM:
+    case K_GEMMT: return 1.7;
+    default: return 1.0;
+  }
+}
+}  // namespace
+
+double static_list_order(Graph &g, int P, int nb) {
+  const int n = (int)g.tasks.size();
+  P = std::max(P, 1);
+  std::vector<double> w(n), bot(n, 0.0);
+  for (int t = 0; t < n; t++) w[t] = g.weight[t] * gpu_cost_per_unit(g.tasks[t].kind, nb);
+  for (int t = n - 1; t >= 0; t--) {  // list order is topological
+    double m = 0.0;
+    for (int e = g.succ_off[t]; e < g.succ_off[t + 1]; e++) m = std::max(m, bot[g.succ[e]]);
+    bot[t] = w[t] + m;
+  }
+  struct Ready {
+    double pri, at;
+    int32_t id;
+    bool operator<(const Ready &o) const {  // max-heap: the "largest" starts first
+      if (pri != o.pri) return pri < o.pri;
+      if (at != o.at) return at > o.at;
+      return id > o.id;
+    }
+  };
+  std::priority_queue<Ready> ready;
+  using Run = std::pair<double, int32_t>;  // (end, id), earliest end first
+  std::priority_queue<Run, std::vector<Run>, std::greater<Run>> running;
+  std::vector<int32_t> deg(g.indeg0.begin(), g.indeg0.end());
+  for (int t = 0; t < n; t++)
+    if (deg[t] == 0) ready.push({bot[t], 0.0, t});
+  std::vector<int32_t> order;
+  order.reserve(n);
+  double now = 0.0, makespan = 0.0;
+  int idle = P;
+  while ((int)order.size() < n || !running.empty()) {
+    while (idle > 0 && !ready.empty()) {
+      const Ready r = ready.top();
+      ready.pop();
+      order.push_back(r.id);
+      running.push({now + w[r.id], r.id});
+      idle--;
+    }
+    if (running.empty()) break;  // (a cycle would stop here; validate() rejects those)
+    now = running.top().first;
+    while (!running.empty() && running.top().first == now) {
+      const int32_t t = running.top().second;
+      running.pop();
+      idle++;
+      makespan = std::max(makespan, now);
+      for (int e = g.succ_off[t]; e < g.succ_off[t + 1]; e++)
+        if (--deg[g.succ[e]] == 0) ready.push({bot[g.succ[e]], now, g.succ[e]});
+    }
+  }
+  g.ready0 = order;
+  g.static_order = true;
+  return makespan;
+}
+
 // --------------------------------------------- tile Cholesky inversion
 Graph build_cholinv_graph(int t, bool inplace, bool udu, bool unit_weights) {
   Graph g;
@@ -621,6 +698,20 @@ bool validate(const Graph &g) {
     }
   for (int t = 0; t < n; t++)
     if (deg[t] != g.indeg0[t]) return false;
+  if (g.static_order) {
+    // every task exactly once, each after all its predecessors
+    if ((int)g.ready0.size() != n) return false;
+    std::vector<int32_t> pos(n, -1);
+    for (int x = 0; x < n; x++) {
+      const int32_t t = g.ready0[x];
+      if (t < 0 || t >= n || pos[t] >= 0) return false;
+      pos[t] = x;
+    }
+    for (int t = 0; t < n; t++)
+      for (int e = g.succ_off[t]; e < g.succ_off[t + 1]; e++)
+        if (pos[g.succ[e]] <= pos[t]) return false;
+    return true;
+  }
   std::vector<int32_t> stack(g.ready0.begin(), g.ready0.end());
   int seen = 0;
   while (!stack.empty()) {

@@ -61,6 +61,9 @@ struct Graph {
   std::vector<double> bottom;  // longest path from the task to an exit, incl. itself
   int64_t nedges = 0;
   double cp = 0.0;
+  // set by static_list_order(): ready0 lists every task, in the order the
+  // executor hands them out
+  bool static_order = false;
 };
 
 // Builds the graph of `list` under `spec`.  zero_t / geqrt_t, when given
@@ -72,6 +75,18 @@ Graph build_graph(const std::vector<Elim> &list, const GraphSpec &spec,
 // Successor lists, dependency counts, bottom levels and the initial ready
 // order (highest bottom level first when `priority`, else list order).
 void finalize(Graph &g, bool priority);
+
+// Simulates the critical-path list schedule of a finalized QR graph on P
+// workgroups with estimated GPU task durations at tile size nb (the
+// tab.kernels weights scaled per kernel by durations measured on MI355X:
+// the panel kernels' Householder steps are latency-bound, so their time per
+// flop is several times the updates' and grows as nb shrinks; a free
+// workgroup starts the ready task of largest bottom level under these
+// durations, ties to the earlier ready time, then the lower index) and sets
+// ready0 to every task in simulated start order, with static_order.  Predecessors always start
+// before their successors in this order.  Returns the simulated makespan
+// (estimated microseconds).
+double static_list_order(Graph &g, int P, int nb);
 
 // Task graph of the tile Cholesky inversion of t x t tiles (thesis chapter
 // "Cholesky Inversion", algorithm alg:InPlace: step 1 the tile Cholesky

@@ -53,7 +53,7 @@ struct ExecCtl {
   int32_t done;    // tasks finished
   int32_t abort;   // set by the watchdog
   int32_t error;   // 0 or TQR_INFO_TIMEOUT
-  int32_t pad[11];
+  int32_t pad[11];  // pad[0]: smallest 1-based index of a zero R(j,j)
 };
 
 // One least-squares / factorization problem as the tile kernels see it.
@@ -81,6 +81,10 @@ struct ExecArgs {
   const int32_t *indeg0;     // initial dependency counts
   const int32_t *ready0;     // initially ready tasks, priority order
   int32_t ntasks, nready0;
+  // nonzero: ready0 lists every task (nready0 == ntasks) in a precomputed
+  // order and the queue is filled once by the reset; a finished task only
+  // decrements its successors' counts
+  int32_t static_order, pad_s;
   // executor state (caller workspace)
   ExecCtl *ctl;
   int32_t *queue;   // ntasks slots

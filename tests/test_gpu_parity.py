@@ -94,6 +94,27 @@ def test_persistent_equals_sequential_bitwise(kernels):
         assert np.array_equal(outs[0][0], outs[1][0])
 
 
+@pytest.mark.parametrize("tree,kernels", [("flat", "hybrid"), ("greedy", "tt"), ("plasma", "hybrid")])
+def test_queue_orders_give_identical_results(tree, kernels):
+    """The static list order changes only the order in which tasks start:
+    the least-squares solution and the factors are identical bit for bit to
+    those of the queue filled as tasks become ready, in both its orders."""
+    for (m, n, nb) in [(1280, 1280, 128), (2000, 700, 64), (3072, 1024, 256)]:
+        case("critical queue %s %s m=%d n=%d nb=%d" % (tree, kernels, m, n, nb))
+        A0 = synth.gaussian(m, n, 21)
+        b0 = synth.gaussian_rhs(m, 1, 21)
+        outs = []
+        for pr in ("static", "bottom", "list"):
+            o = T.default_opts(nb=nb, tree=tree, param=2 if tree == "plasma" else 0, kernels=kernels,
+                               priority=pr)
+            X = T.lstsq(T.colmajor(A0), T.colmajor(b0), o)
+            A, W = _factor(A0, o)
+            outs.append((X.cpu().numpy(), A.cpu().numpy()))
+        for x in outs[1:]:
+            assert np.array_equal(outs[0][0], x[0]) and np.array_equal(outs[0][1], x[1])
+        assert H.ls_backward_error(A0, b0[:, 0], outs[0][0][:, 0]) <= 50 * EPS
+
+
 @pytest.mark.parametrize("stripes", [1, 2, 4, 8])
 def test_stripes_do_not_change_results(stripes):
     case("stripes %d" % stripes)
@@ -195,14 +216,16 @@ def test_tall_skinny_full_size_five_trees():
         assert np.max(np.abs(dg - diags[0]) / diags[0]) <= 1e-10
 
 
-@pytest.mark.parametrize("kernels", ["tt", "hybrid"])
-def test_executor_trace_respects_dependencies(kernels):
+@pytest.mark.parametrize("kernels,priority", [("tt", "bottom"), ("hybrid", "bottom"), ("tt", "static"),
+                                               ("hybrid", "static")])
+def test_executor_trace_respects_dependencies(kernels, priority):
     """Post-hoc check of a normal run: with per-task clock stamps on, every
     task of the least-squares graph ran, and no task started before any of
-    its predecessors had ended (the executor's data-flow contract)."""
+    its predecessors had ended (the executor's data-flow contract), with one
+    ready queue filled as tasks become ready and with the static list order."""
     for (m, n, nb, ib) in [(1000, 333, 64, 16), (2048, 768, 256, 32)]:
-        case("trace %s m=%d n=%d nb=%d" % (kernels, m, n, nb))
-        o = T.default_opts(nb=nb, ib=ib, tree="greedy", kernels=kernels)
+        case("trace %s %s m=%d n=%d nb=%d" % (kernels, priority, m, n, nb))
+        o = T.default_opts(nb=nb, ib=ib, tree="greedy", kernels=kernels, priority=priority)
         nt = len(T.debug_graph(m, n, o, nrhs=1, kind=3))
         off, succ = T.debug_succ(m, n, o, nrhs=1, kind=3)
         buf = torch.zeros(4 * nt, dtype=torch.int64, device="cuda")
@@ -218,14 +241,15 @@ def test_executor_trace_respects_dependencies(kernels):
         assert H.ls_backward_error(A0, b0[:, 0], X.cpu().numpy()[:, 0]) <= 50 * EPS
 
 
-def test_watchdog_fires_and_the_executor_drains():
+@pytest.mark.parametrize("priority", ["bottom", "static"])
+def test_watchdog_fires_and_the_executor_drains(priority):
     """Failure handling forced from the host: with a watchdog limit of one
     clock tick, a workgroup that finds its queue slot not yet filled aborts
     the launch; every workgroup then leaves, info reports the timeout, and
     the next launch (default limit) is correct again."""
-    case("watchdog")
+    case("watchdog %s" % priority)
     A0 = synth.gaussian(512, 256, 4)
-    o = T.default_opts(nb=128, tree="greedy")
+    o = T.default_opts(nb=128, tree="flat", kernels="hybrid", priority=priority)
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
     T.debug_spin_limit(1)
     try:
