@@ -64,6 +64,17 @@ struct PlanKey {
   }
 };
 
+// Where the static list order pays (measured on MI355X): at nb >= 128
+// always (8192^2: 39.6 -> 35.1 ms, 16384 x 2048: 17.3 -> 16.7 ms, batches
+// of ragged problems 26.8 -> 22.8 ms); at nb 64 on graphs of up to 64 tasks
+// per workgroup (4096 x 1024: 6.4 -> 5.0 ms) but not on larger ones
+// (16384 x 2048: 20.1 -> 22.3 ms), whose many short tasks keep workgroups
+// busier when taken as they become ready.  Elsewhere the queue is filled
+// dynamically in bottom-level order.
+bool use_static_order(int nb, size_t ntasks, int P) {
+  return nb >= 128 || ntasks <= (size_t)64 * (size_t)std::max(P, 1);
+}
+
 struct HostPlan {
   Graph g;
   bool valid = false;
@@ -121,7 +132,8 @@ std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
   if (!solve_kind(k.kind)) list = make_list(k.tree, k.p, k.q, k.param);
   hp->g = build_graph(list, spec);
   finalize(hp->g, k.priority != 0);
-  if (k.priority == TQR_PRIO_STATIC && k.kind != PK_ZFACTOR && k.kind != PK_ZAPPLY)
+  if (k.priority == TQR_PRIO_STATIC && k.kind != PK_ZFACTOR && k.kind != PK_ZAPPLY &&
+      use_static_order(k.nb, hp->g.tasks.size(), k.P))
     static_list_order(hp->g, k.P, k.nb);
   hp->valid = validate(hp->g);
   // the host structure is only needed for sequential order and statistics
@@ -545,9 +557,7 @@ BatchKey batch_key(int kind, int count, const int64_t *m, const int64_t *n, int6
   k.ib = r.ib;
   k.family = solve_kind(kind) ? 0 : r.family;
   k.stripes = r.stripes;
-  // the concatenated graph is pushed dynamically: its parts keep their
-  // initially ready tasks (no static order)
-  k.priority = std::min(r.priority, (int)TQR_PRIO_BOTTOM);
+  k.priority = r.priority;
   k.nrhs = nrhs;
   k.shape.reserve((size_t)count * 4);
   for (int x = 0; x < count; x++) {
@@ -576,10 +586,14 @@ std::shared_ptr<BatchPlan> batch_plan(const BatchKey &k, const Resolved &r, int 
   std::vector<Task> tasks;
   std::vector<int32_t> off(1, 0), succ, indeg0;
   std::vector<std::pair<double, int32_t>> ready;
+  // with the static order, the list schedule is simulated over the whole
+  // concatenated graph (the parts are built with their dynamic ready sets)
+  const bool stat = k.priority == TQR_PRIO_STATIC;
+  std::vector<double> weight;
   bool valid = true;
   for (int x = 0; x < count; x++) {
     Resolved rx = r;
-    rx.priority = k.priority;
+    rx.priority = std::min(k.priority, (int)TQR_PRIO_BOTTOM);
     rx.tree = k.shape[4 * x + 2];
     rx.param = k.shape[4 * x + 3];
     auto hp = host_plan(make_key(k.kind, k.shape[4 * x], k.shape[4 * x + 1], k.kind == PK_FACTOR ? 0 : k.nrhs, rx));
@@ -594,6 +608,7 @@ std::shared_ptr<BatchPlan> batch_plan(const BatchKey &k, const Resolved &r, int 
       off.push_back((int32_t)succ.size());
       indeg0.push_back(g.indeg0[t]);
       bp->order.push_back(base + (int32_t)t);
+      if (stat) weight.push_back(g.weight[t]);
     }
     for (int32_t t : g.ready0) ready.push_back({g.bottom[t], base + t});
   }
@@ -603,6 +618,19 @@ std::shared_ptr<BatchPlan> batch_plan(const BatchKey &k, const Resolved &r, int 
                    });
   std::vector<int32_t> ready0;
   for (auto &pr : ready) ready0.push_back(pr.second);
+  bool in_order = false;  // ready0 holds every task in the static order
+  if (stat && valid && use_static_order(k.nb, tasks.size(), grid_size(dev, k.nb, k.ib))) {
+    in_order = true;
+    Graph cg;
+    cg.tasks = tasks;
+    cg.weight = std::move(weight);
+    cg.succ_off = off;
+    cg.succ = succ;
+    cg.indeg0 = indeg0;
+    static_list_order(cg, grid_size(dev, k.nb, k.ib), k.nb);
+    valid = validate(cg);
+    ready0 = std::move(cg.ready0);
+  }
   DevicePlan &d = bp->d;
   if (upload(&d.tasks, tasks) != hipSuccess || upload(&d.succ_off, off) != hipSuccess ||
       upload(&d.succ, succ) != hipSuccess || upload(&d.indeg0, indeg0) != hipSuccess ||
@@ -610,6 +638,7 @@ std::shared_ptr<BatchPlan> batch_plan(const BatchKey &k, const Resolved &r, int 
     valid = false;
   d.ntasks = (int32_t)tasks.size();
   d.nready0 = (int32_t)ready0.size();
+  d.static_order = in_order ? 1 : 0;
   bp->valid = valid;
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_batch.find({dev, k});
@@ -723,6 +752,7 @@ int launch_batch(const BatchPlan &bp, const Resolved &r, int count, ExecCtl *ctl
   a.ready0 = bp.d.ready0;
   a.ntasks = bp.d.ntasks;
   a.nready0 = bp.d.nready0;
+  a.static_order = bp.d.static_order;
   char *st = reinterpret_cast<char *>(ctl);
   a.ctl = ctl;
   a.queue = reinterpret_cast<int32_t *>(st + align_up(sizeof(ExecCtl)));

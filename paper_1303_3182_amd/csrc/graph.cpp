@@ -427,24 +427,26 @@ void finalize(Graph &g, bool priority) {
 }
 
 namespace {
-// Estimated GPU duration per unit of tab.kernels weight (arbitrary time
-// unit), from per-task traces on MI355X at nb 128 (GEQRT 148 us, TSQRT
-// 185, UNMQR 51, TSMQR 72, TRSM 20, GEMM 10 with one right-hand side) and
-// nb 256 (TTQRT 2.2 x, TTMQR 1.2 x GEQRT's / UNMQR's time per unit).
-// Panel kernels scale with 128 / nb per unit.
+// Estimated GPU duration (microseconds) per unit of tab.kernels weight, from
+// the mean task durations of traced least-squares launches on MI355X (TRSM
+// and GEMM with one right-hand side), per tile size; nb 32 takes nb 64's.
 double gpu_cost_per_unit(int kind, int nb) {
-  const double panel = 128.0 / (double)nb;
+  //                              GEQRT  TSQRT  TTQRT  UNMQR  TSMQR  TTMQR  TRSM  GEMM
+  static const double c64[8] = {17.8, 13.5, 37.5, 4.4, 2.2, 3.8, 9.0, 1.0};
+  static const double c128[8] = {37.0, 31.0, 74.0, 8.3, 6.0, 9.6, 20.0, 1.7};
+  static const double c256[8] = {134.0, 126.0, 247.0, 54.0, 41.0, 62.0, 42.0, 3.6};
+  const double *c = nb >= 256 ? c256 : (nb >= 128 ? c128 : c64);
   switch (kind) {
-    case K_GEQRT: return 37.0 * panel;
-    case K_TSQRT: return 31.0 * panel;
-    case K_TTQRT: return 69.0 * panel;
-    case K_UNMQR: return 8.5;
-    case K_TSMQR: return 6.0;
-    case K_TTMQR: return 10.0;
+    case K_GEQRT: return c[0];
+    case K_TSQRT: return c[1];
+    case K_TTQRT: return c[2];
+    case K_UNMQR: return c[3];
+    case K_TSMQR: return c[4];
+    case K_TTMQR: return c[5];
     case K_TRSM:
-    case K_TRSMT: return 20.0;
+    case K_TRSMT: return c[6];
     case K_GEMM:
-    case K_GEMMT: return 1.7;
+    case K_GEMMT: return c[7];
     default: return 1.0;
   }
 }

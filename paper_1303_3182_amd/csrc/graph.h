@@ -78,10 +78,10 @@ void finalize(Graph &g, bool priority);
 
 // Simulates the critical-path list schedule of a finalized QR graph on P
 // workgroups with estimated GPU task durations at tile size nb (the
-// tab.kernels weights scaled per kernel by durations measured on MI355X:
-// the panel kernels' Householder steps are latency-bound, so their time per
-// flop is several times the updates' and grows as nb shrinks; a free
-// workgroup starts the ready task of largest bottom level under these
+// tab.kernels weights scaled per kernel by task durations measured on
+// MI355X at nb 64, 128 and 256: the panel kernels' Householder steps are
+// latency-bound, so their time per flop is 2.5 to 4 times the updates'; a
+// free workgroup starts the ready task of largest bottom level under these
 // durations, ties to the earlier ready time, then the lower index) and sets
 // ready0 to every task in simulated start order, with static_order.  Predecessors always start
 // before their successors in this order.  Returns the simulated makespan

@@ -442,7 +442,7 @@ __device__ __forceinline__ void apply_chunk_lp(const double *__restrict__ V, int
                                                int ncols, bool dma, Smem<NB, IB, WC> &sm) {
   constexpr int NRB = NB / 16;
   constexpr int NMB = IB / 16;
-  constexpr int NBLK = NB / IB;
+  const int NBLK = (vcols + IB - 1) / IB;  // blocks that hold reflectors
   constexpr int LDV = Smem<NB, IB, WC>::LDV;
   constexpr int LDT = Smem<NB, IB, WC>::LDT;
   const int tid = opaque_tid();
@@ -941,11 +941,16 @@ __device__ __forceinline__ void panel_block_at(int b, double *Vt, int64_t ldv, i
     panel_block_at<NB, IB, WC, MODE, B + 1>(b, Vt, ldv, vrows, R1, ldr, ncols, Tout, sm);
 }
 
+// Only the inner blocks that hold columns of the matrix are factored (a
+// ragged last tile column has ncols < NB); the later blocks hold no
+// reflectors and get a zero T.
 template <int NB, int IB, int WC, int MODE>
 __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, double *R1,
                                            int64_t ldr, int ncols, double *Tout,
                                            Smem<NB, IB, WC> &sm) {
-  for (int b = 0; b < NB / IB; b++) panel_block_at<NB, IB, WC, MODE>(b, Vt, ldv, vrows, R1, ldr, ncols, Tout, sm);
+  const int nblk = (ncols + IB - 1) / IB;
+  for (int b = 0; b < nblk; b++) panel_block_at<NB, IB, WC, MODE>(b, Vt, ldv, vrows, R1, ldr, ncols, Tout, sm);
+  for (int idx = nblk * IB * IB + opaque_tid(); idx < NB * IB; idx += NT) Tout[idx] = 0.0;
 }
 
 // ============================================================ solve kernels
@@ -1511,6 +1516,24 @@ __device__ __forceinline__ void run_task(const Problem &a, const Task &t, Smem<N
         else
           apply_chunk_lp<NB, IB, WC, M_TS, P_BF16>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld,
                                                    vrows, nc, dma, sm);
+      }
+      continue;
+    }
+    // A ragged last tile column: only its blocks that hold reflectors, with
+    // a runtime block loop.
+    if (vcols < NB) {
+      const int nblk = (vcols + IB - 1) / IB;
+      if (kind == K_UNMQR) {
+        apply_chunk<NB, IB, WC, M_UNM>(V, lda, vrows, vcols, Tof(t.i, t.k, 0), nullptr, 0, C2, ld, vrows, nc, 0,
+                                       nblk, false, dma, sm);
+      } else {
+        double *C1 = base + (int64_t)cs * ld + (int64_t)t.piv * NB;
+        if (kind == K_TTMQR)
+          apply_chunk<NB, IB, WC, M_TT>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld, vrows, nc, 0,
+                                        nblk, false, dma, sm);
+        else
+          apply_chunk<NB, IB, WC, M_TS>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld, vrows, nc, 0,
+                                        nblk, false, dma, sm);
       }
       continue;
     }
