@@ -87,6 +87,18 @@ struct DevicePlan {
   int32_t static_order = 0;        // ready0 is a precomputed order of every task
 };
 
+// The graph fields of an executor launch, from its device plan.
+void set_plan(ExecArgs &a, const DevicePlan &d) {
+  a.tasks = d.tasks;
+  a.succ_off = d.succ_off;
+  a.succ = d.succ;
+  a.indeg0 = d.indeg0;
+  a.ready0 = d.ready0;
+  a.ntasks = d.ntasks;
+  a.nready0 = d.nready0;
+  a.static_order = d.static_order;
+}
+
 std::mutex g_mu;
 std::map<PlanKey, std::shared_ptr<HostPlan>> g_host;
 std::map<std::pair<int, PlanKey>, DevicePlan> g_dev;
@@ -108,6 +120,7 @@ std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
   if (k.kind == PK_CHOLINV) {
     hp->g = build_cholinv_graph(k.p, k.family == 0, k.tree == 0);
     finalize(hp->g, true);
+    if (k.priority == TQR_PRIO_STATIC) static_list_order(hp->g, k.P, k.nb);
     hp->valid = validate(hp->g);
     hp->g.preds.clear();
     hp->g.preds.shrink_to_fit();
@@ -132,8 +145,7 @@ std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
   if (!solve_kind(k.kind)) list = make_list(k.tree, k.p, k.q, k.param);
   hp->g = build_graph(list, spec);
   finalize(hp->g, k.priority != 0);
-  if (k.priority == TQR_PRIO_STATIC && k.kind != PK_ZFACTOR && k.kind != PK_ZAPPLY &&
-      use_static_order(k.nb, hp->g.tasks.size(), k.P))
+  if (k.priority == TQR_PRIO_STATIC && use_static_order(k.nb, hp->g.tasks.size(), k.P))
     static_list_order(hp->g, k.P, k.nb);
   hp->valid = validate(hp->g);
   // the host structure is only needed for sequential order and statistics
@@ -188,6 +200,15 @@ int grid_size(int dev, int nb, int ib) {
   const int grid = cus * std::max(1, occ);
   g_grid[dev * 1024 + nb * 4 + ib / 16] = grid;
   return grid;
+}
+
+// Compute units of the current device (256, MI355X's, when none is visible).
+int device_cus() {
+  int count = 0, dev = 0, cus = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1 || hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return 256;
+  return cus;
 }
 
 // Executor workgroups on the current device, the P of the static list
@@ -389,14 +410,7 @@ int run_plan(int kind, int64_t m, int64_t n, double *A, int64_t lda, double *B, 
   }
   char *base = static_cast<char *>(T);
   ExecArgs a{};
-  a.tasks = dp.tasks;
-  a.succ_off = dp.succ_off;
-  a.succ = dp.succ;
-  a.indeg0 = dp.indeg0;
-  a.ready0 = dp.ready0;
-  a.ntasks = dp.ntasks;
-  a.nready0 = dp.nready0;
-  a.static_order = dp.static_order;
+  set_plan(a, dp);
   char *st = base + kHeader + align_up(tf);
   a.ctl = reinterpret_cast<ExecCtl *>(st);
   a.queue = reinterpret_cast<int32_t *>(st + align_up(sizeof(ExecCtl)));
@@ -745,14 +759,7 @@ int launch_batch(const BatchPlan &bp, const Resolved &r, int count, ExecCtl *ctl
                  int32_t *info, const int32_t *skip, int dev, hipStream_t stream, size_t state_bytes_) {
   (void)state_bytes_;
   ExecArgs a{};
-  a.tasks = bp.d.tasks;
-  a.succ_off = bp.d.succ_off;
-  a.succ = bp.d.succ;
-  a.indeg0 = bp.d.indeg0;
-  a.ready0 = bp.d.ready0;
-  a.ntasks = bp.d.ntasks;
-  a.nready0 = bp.d.nready0;
-  a.static_order = bp.d.static_order;
+  set_plan(a, bp.d);
   char *st = reinterpret_cast<char *>(ctl);
   a.ctl = ctl;
   a.queue = reinterpret_cast<int32_t *>(st + align_up(sizeof(ExecCtl)));
@@ -1559,7 +1566,9 @@ PlanKey zkey(int kind, int64_t m, int64_t n, int64_t nrhs, const ZResolved &z) {
   k.tree = z.tree;
   k.param = z.param;
   k.stripes = k.stripes_b = 1;
-  k.priority = 1;
+  // the dynamic queue: the static order with the real kernels' costs was
+  // slower on the 8192 x 2048 complex QR (76.7 against 76.2 ms)
+  k.priority = TQR_PRIO_BOTTOM;
   return k;
 }
 
@@ -1600,13 +1609,7 @@ int zrun(int kind, int64_t m, int64_t n, void *A, int64_t lda, void *B, int64_t 
   }
   char *w = static_cast<char *>(W);
   ExecArgs a{};
-  a.tasks = dp.tasks;
-  a.succ_off = dp.succ_off;
-  a.succ = dp.succ;
-  a.indeg0 = dp.indeg0;
-  a.ready0 = dp.ready0;
-  a.ntasks = dp.ntasks;
-  a.nready0 = dp.nready0;
+  set_plan(a, dp);
   a.ctl = reinterpret_cast<ExecCtl *>(w + tb);
   a.queue = reinterpret_cast<int32_t *>(w + tb + align_up(sizeof(ExecCtl)));
   a.indeg = reinterpret_cast<int32_t *>(w + tb + align_up(sizeof(ExecCtl)) +
@@ -1692,7 +1695,16 @@ PlanKey cholinv_key(int64_t n, int nb, int variant) {
   k.family = variant & TQR_CHOLINV_RENAMED ? 1 : 0;
   k.tree = variant & TQR_CHOLINV_UUU ? 1 : 0;
   k.stripes = k.stripes_b = 1;
-  k.priority = 1;
+  // the static list order (tab units as durations) for the in-place graph
+  // (4096^2, nb 64: 26.7 -> 24.3 ms), the dynamic queue for the renamed one
+  // (21.8 ms, 22.8 in the static order)
+  if (k.family == 0) {
+    k.priority = TQR_PRIO_STATIC;
+    k.nb = nb;
+    k.P = device_cus() * cholinv_occupancy(nb);
+  } else {
+    k.priority = TQR_PRIO_BOTTOM;
+  }
   return k;
 }
 
@@ -1759,13 +1771,7 @@ int tqr_cholinv(int64_t n, double *A, int64_t lda, int32_t nb, int32_t variant, 
   }
   char *w = static_cast<char *>(work);
   ExecArgs a{};
-  a.tasks = dp.tasks;
-  a.succ_off = dp.succ_off;
-  a.succ = dp.succ;
-  a.indeg0 = dp.indeg0;
-  a.ready0 = dp.ready0;
-  a.ntasks = dp.ntasks;
-  a.nready0 = dp.nready0;
+  set_plan(a, dp);
   a.ctl = reinterpret_cast<ExecCtl *>(w + L.state);
   a.queue = reinterpret_cast<int32_t *>(w + L.state + align_up(sizeof(ExecCtl)));
   a.indeg = reinterpret_cast<int32_t *>(w + L.state + align_up(sizeof(ExecCtl)) +

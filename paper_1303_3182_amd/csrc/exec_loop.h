@@ -123,7 +123,11 @@ __device__ __forceinline__ void executor_loop(const ExecArgs &a, int *slot, Run 
         if (__hip_atomic_fetch_add(&a.indeg[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1 &&
             !a.static_order) {
           const int q = __hip_atomic_fetch_add(&ctl->tail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&a.queue[q], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          // every task is pushed at most once, so q < ntasks unless the
+          // launch's queue was filled up front without static_order set; a
+          // push past the end is dropped (the watchdog then reports it)
+          // rather than written over the dependency counts
+          if (q < a.ntasks) __hip_atomic_store(&a.queue[q], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
       __hip_atomic_fetch_add(&ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
