@@ -565,14 +565,17 @@ def run_batched(args, np, torch, T, synth):
         bes = [H.ls_backward_error(As[x], Bs[x][:, 0], Xs[x][:, 0].cpu().numpy()) for x in sample]
         reps = T.refine_reports(work, len(shapes)) if dt != "f64" else []
         results[dt] = {"ms_per_step": ms, "value": flops / (ms / 1e3) / 1e12, "executor_ms": kms,
-                       "launches_per_step": nl, "nb": o.nb, "ib": o.ib, "autotune_best_ms": tune_ms,
+                       "launches_per_step": nl, "nb": o.nb, "ib": o.ib,
+                       "kernels": {T.TT: "tt", T.HYBRID: "ts"}.get(o.kernels, o.kernels),
+                       "tree": [k for k, v in T.TREES.items() if v == o.tree][0] if o.tree in T.TREES.values()
+                       else "per-problem", "tree_param": o.param, "autotune_best_ms": tune_ms,
                        "problems_with_info": bad, "max_backward_error_sample": max(bes),
                        "sample_problems": len(sample), "equal_fp64_error": bool(max(bes) <= 50 * EPS)}
         if reps:
             results[dt]["max_refine_steps"] = max(r["iterations"] for r in reps)
             results[dt]["converged"] = sum(r["done"] for r in reps)
-        log("batched %s: nb=%d ib=%d %.2f ms/step (%.2f TFLOP/s), max be %.2e" %
-            (dt, o.nb, o.ib, ms, flops / (ms / 1e3) / 1e12, max(bes)))
+        log("batched %s: nb=%d ib=%d kernels=%d tree=%d/%d %.2f ms/step (%.2f TFLOP/s), max be %.2e" %
+            (dt, o.nb, o.ib, o.kernels, o.tree, o.param, ms, flops / (ms / 1e3) / 1e12, max(bes)))
     for dt in args.mixed:
         results[dt]["speedup_vs_fp64"] = results["f64"]["ms_per_step"] / results[dt]["ms_per_step"]
     lead = args.mixed[0] if args.mixed else "f64"
@@ -580,7 +583,7 @@ def run_batched(args, np, torch, T, synth):
     out = base_line(args, r0["value"], r0["ms_per_step"], lead,
                     {"workload": "batched ragged least squares: %d problems, m log-uniform [256, 8192], "
                                  "n log-uniform [32, 512], n <= m/2, N(0,1), seed 0; %s updates + FP64 "
-                                 "refinement; autotuned nb/ib, tree per problem" % (len(shapes), lead),
+                                 "refinement; autotuned nb/ib, kernel family and tree policy" % (len(shapes), lead),
                      "problems": len(shapes), "qr_flops": flops})
     out["per_dtype"] = results
     out["roofline"] = roofline(flops, r0["executor_ms"] * r0["launches_per_step"],

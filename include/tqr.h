@@ -231,18 +231,25 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
  * -2 bad m / n, -4 nrhs < 1, -5 bad A / lda, -7 bad B / ldb, -9 bad X / ldx,
  * -11 work NULL. */
 size_t tqr_lstsq_batched_work_size(int32_t count, const int64_t *m, const int64_t *n, int64_t nrhs,
-                                   const tqr_opts *o); /* o->nb == 0: largest over the built configs */
+                                   const tqr_opts *o); /* o->nb == 0: largest over the built configs
+                                                          (and, with TQR_AUTO, the autotuner's tree
+                                                          policies) */
 int tqr_lstsq_batched(int32_t count, const int64_t *m, const int64_t *n, int64_t nrhs,
                       const double *const *A, const int64_t *lda, const double *const *B,
                       const int64_t *ldb, double *const *X, const int64_t *ldx, void *work,
                       size_t work_bytes, const tqr_opts *o, int32_t *info, hipStream_t stream);
 
 /* Autotuner for a batch: runs tqr_lstsq_batched with every built (nb, ib)
- * configuration (tree and the other options from *o), times each on
- * `stream` with HIP events, and writes the fastest nb, ib into *o
- * (best_ms: NULL or its time).  Synchronous.  The choice is cached per
- * (shapes, nrhs, options); a cached call returns at once with *best_ms =
- * -1.  work must hold tqr_lstsq_batched_work_size with o->nb = 0.  X
+ * configuration, times each on `stream` with HIP events, and writes the
+ * fastest into *o (best_ms: NULL or its time).  With o->tree == TQR_AUTO it
+ * also tries the kernel family and tree policy: the per-problem
+ * critical-path tree with TT or TS kernels, and PlasmaTree with domains of
+ * 4 or 8 tile rows and TS kernels; the fastest is written into o->kernels,
+ * o->tree and o->param.  Otherwise the tree and family are the options'.
+ * Synchronous.  The choice is cached per (shapes, nrhs, options), under
+ * the options given and those chosen; a cached call returns at once with
+ * *best_ms = -1.  work must hold tqr_lstsq_batched_work_size with
+ * o->nb = 0 (which covers every configuration and policy tried).  X
  * receives the solutions of the last run. */
 int tqr_autotune_batched(int32_t count, const int64_t *m, const int64_t *n, int64_t nrhs,
                          const double *const *A, const int64_t *lda, const double *const *B,

@@ -537,6 +537,21 @@ std::map<std::pair<int, BatchKey>, std::shared_ptr<BatchPlan>> g_batch;
 
 // Tree with the shortest tiled critical path for p x q tiles (the thesis's
 // own measure of a tree, section "Critical paths"), among the five trees.
+// Kernel family and tree the batch autotuner tries besides (nb, ib): the
+// options' own when they name a tree; with TQR_AUTO, the per-problem
+// critical-path choice with either family and PlasmaTree domains of 4 and
+// 8 tile rows with TS kernels (a batch keeps every CU busy, so kernels that
+// do less work per tile can beat shorter critical paths: 512 ragged
+// problems at nb 256, 21.8 ms with the per-problem choice and TT kernels,
+// 18.9 ms with TS kernels, 17.1 ms with PlasmaTree BS 4 and TS kernels).
+struct TreePolicy {
+  int family, tree, param;
+};
+std::vector<TreePolicy> batch_tree_policies(const tqr_opts &o) {
+  if (o.tree != TQR_AUTO) return {{o.kernels, o.tree, o.param}};
+  return {{TQR_TT, TQR_AUTO, 0}, {TQR_HYBRID, TQR_AUTO, 0}, {TQR_HYBRID, TQR_PLASMA, 4}, {TQR_HYBRID, TQR_PLASMA, 8}};
+}
+
 int auto_tree(int p, int q, int family) {
   static std::map<std::tuple<int, int, int>, int> cache;
   {
@@ -1151,27 +1166,34 @@ size_t tqr_lstsq_batched_work_size(int32_t count, const int64_t *m, const int64_
   if (check_batch(count, m, n, nrhs)) return 0;
   tqr_opts d;
   tqr_default_opts(&d);
-  tqr_opts x = o ? *o : d;
+  const tqr_opts x0 = o ? *o : d;
   int nbs[16], ibs[16];
   int nc = 1;
-  if (x.nb == 0) {
+  if (x0.nb == 0) {
     nc = std::min(config_list(nbs, ibs, 16), 16);
   } else {
-    nbs[0] = x.nb;
-    ibs[0] = x.ib;
+    nbs[0] = x0.nb;
+    ibs[0] = x0.ib;
   }
   size_t best = 0;
-  const int tree_opt = x.tree;
-  if (x.tree == TQR_AUTO) x.tree = TQR_GRASAP;  // per-problem choice below; nb from opts
-  for (int c = 0; c < nc; c++) {
-    x.nb = nbs[c];
-    x.ib = ibs[c];
-    Resolved r;
-    if (resolve(&x, &r)) return 0;
-    const BatchKey kf = batch_key(PK_LSTSQ, count, m, n, nrhs, r, tree_opt);
-    const BatchKey ks = batch_key(PK_SNE, count, m, n, nrhs, r, tree_opt);
-    best = std::max(best, batch_layout(count, m, n, nrhs, r, kf, ks).total);
-  }
+  // with nb == 0 (the autotuner's workspace): also over its tree policies
+  const std::vector<TreePolicy> pol = x0.nb == 0 ? batch_tree_policies(x0)
+                                                 : std::vector<TreePolicy>{{x0.kernels, x0.tree, x0.param}};
+  for (const TreePolicy &tp : pol)
+    for (int c = 0; c < nc; c++) {
+      tqr_opts x = x0;
+      x.nb = nbs[c];
+      x.ib = ibs[c];
+      x.kernels = tp.family;
+      x.param = tp.param;
+      const int tree_opt = tp.tree;
+      x.tree = tp.tree == TQR_AUTO ? TQR_GRASAP : tp.tree;  // per-problem choice below; nb from opts
+      Resolved r;
+      if (resolve(&x, &r)) return 0;
+      const BatchKey kf = batch_key(PK_LSTSQ, count, m, n, nrhs, r, tree_opt);
+      const BatchKey ks = batch_key(PK_SNE, count, m, n, nrhs, r, tree_opt);
+      best = std::max(best, batch_layout(count, m, n, nrhs, r, kf, ks).total);
+    }
   return best;
 }
 
@@ -1330,32 +1352,47 @@ int tqr_autotune_batched(int32_t count, const int64_t *m, const int64_t *n, int6
   if (!o) return -13;
   int rc = check_batch(count, m, n, nrhs);
   if (rc) return rc;
-  static std::map<std::vector<int64_t>, std::pair<int, int>> cache;
-  std::vector<int64_t> sig = {count, nrhs, o->tree, o->kernels, o->update_dtype, o->param, o->stripes};
-  for (int x = 0; x < count; x++) {
-    sig.push_back(m[x]);
-    sig.push_back(n[x]);
-  }
+  // the choice (nb, ib, kernels, tree, param), cached under the options
+  // given and under the options chosen
+  static std::map<std::vector<int64_t>, std::array<int, 5>> cache;
+  auto signature = [&](const tqr_opts &q) {
+    std::vector<int64_t> sig = {count, nrhs, q.tree, q.kernels, q.update_dtype, q.param, q.stripes};
+    for (int x = 0; x < count; x++) {
+      sig.push_back(m[x]);
+      sig.push_back(n[x]);
+    }
+    return sig;
+  };
+  const std::vector<int64_t> sig = signature(*o);
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = cache.find(sig);
     if (it != cache.end()) {
-      o->nb = it->second.first;
-      o->ib = it->second.second;
+      o->nb = it->second[0];
+      o->ib = it->second[1];
+      o->kernels = it->second[2];
+      o->tree = it->second[3];
+      o->param = it->second[4];
       if (best_ms) *best_ms = -1.0f;
       return TQR_OK;
     }
   }
   int nbs[16], ibs[16];
   const int nc = std::min(config_list(nbs, ibs, 16), 16);
+  const std::vector<TreePolicy> pol = batch_tree_policies(*o);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TQR_E_HIP;
   float bms = 1e30f;
   int bnb = 0, bib = 0;
-  for (int c = 0; c < nc; c++) {
+  TreePolicy bpol = pol[0];
+  for (int c = 0; c < nc * (int)pol.size(); c++) {
     tqr_opts x = *o;
-    x.nb = nbs[c];
-    x.ib = ibs[c];
+    x.nb = nbs[c % nc];
+    x.ib = ibs[c % nc];
+    const TreePolicy &tp = pol[c / nc];
+    x.kernels = tp.family;
+    x.tree = tp.tree;
+    x.param = tp.param;
     // first run builds and uploads the plans; the second is timed
     rc = tqr_lstsq_batched(count, m, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, &x, nullptr, stream);
     if (rc == TQR_E_WORKSPACE) continue;
@@ -1373,6 +1410,7 @@ int tqr_autotune_batched(int32_t count, const int64_t *m, const int64_t *n, int6
       bms = ms;
       bnb = x.nb;
       bib = x.ib;
+      bpol = tp;
     }
   }
   hipEventDestroy(e0);
@@ -1381,9 +1419,14 @@ int tqr_autotune_batched(int32_t count, const int64_t *m, const int64_t *n, int6
   if (bnb == 0) return TQR_E_WORKSPACE;
   o->nb = bnb;
   o->ib = bib;
+  o->kernels = bpol.family;
+  o->tree = bpol.tree;
+  o->param = bpol.param;
   if (best_ms) *best_ms = bms;
+  const std::array<int, 5> choice = {bnb, bib, bpol.family, bpol.tree, bpol.param};
   std::lock_guard<std::mutex> lk(g_mu);
-  cache[sig] = {bnb, bib};
+  cache[sig] = choice;
+  cache[signature(*o)] = choice;
   return TQR_OK;
 }
 
