@@ -400,9 +400,12 @@ def run_square(args, np, torch, T, synth):
     out = base_line(args, qr_flops(n, n) / (fp64["ms"] / 1e3) / 1e12, fp64["ms"], "f64",
                     {"workload": "FP64 tiled-QR least squares of square %dx%d systems with prescribed condition "
                                  "number (Haar U, V; log-spaced sigma; b = A x + 1e-6 N(0,1)), nb=%d (%dx%d tiles), "
-                                 "%s tree, %s kernels" % (n, n, nb, -(-n // nb), -(-n // nb), tree,
-                                                          "TS" if kernels == "hybrid" and tree == "flat"
-                                                          else kernels.upper()),
+                                 "%s, %s kernels" % (n, n, nb, -(-n // nb), -(-n // nb),
+                                                     "PlasmaTree(BS=%d)" % param if tree == "plasma"
+                                                     else tree + " tree",
+                                                     "TS" if kernels == "hybrid" and tree == "flat"
+                                                     else ("TS domains, TT merges" if kernels == "hybrid"
+                                                           else kernels.upper())),
                      "n": n, "nb": nb, "ib": ib, "tree": tree, "param": param, "kernels": kernels,
                      "kappas": args.kappas, "precision": "plain FP64"})
     out["executor_ms"] = fp64["kms"]
@@ -607,11 +610,12 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--square-n", type=int, default=8192)
     # square workload configuration (measured fastest among the trees, both
-    # kernel families and nb 64 / 128 / 256 on this workload)
+    # kernel families, PlasmaTree domain sizes and nb 64 / 128 / 256 on this
+    # workload: PlasmaTree with TS domains of 48 tile rows and TT merges)
     ap.add_argument("--square-nb", type=int, default=128)
     ap.add_argument("--square-ib", type=int, default=32)
-    ap.add_argument("--square-tree", default="flat")
-    ap.add_argument("--square-param", type=int, default=0)
+    ap.add_argument("--square-tree", default="plasma")
+    ap.add_argument("--square-param", type=int, default=48)
     ap.add_argument("--square-kernels", default="hybrid")
     ap.add_argument("--kappas", type=float, nargs="*", default=[1e2, 1e5, 1e8])
     ap.add_argument("--batch", type=int, default=512)

@@ -1,6 +1,7 @@
 """Parity at the workloads' full sizes, in the launch configuration the
-benchmark times (square systems: nb 128, ib 32, FlatTree with the hybrid
-family, i.e. the pure TS algorithm; persistent executor).
+benchmark times (square systems: nb 128, ib 32, PlasmaTree with TS
+domains of 48 tile rows merged by TT kernels; persistent executor in the
+static list order).
 
 Square 8192 x 8192 systems with prescribed condition number (A = U diag(s)
 V^T, Haar U and V, log-spaced s; b = A x + 1e-6 N(0,1)):
@@ -29,7 +30,7 @@ from tests.gpu_util import EPS, case, r_tol
 pytestmark = pytest.mark.gpu
 
 N, NB = 8192, 128
-SQ = dict(nb=NB, ib=32, tree="flat", kernels="hybrid")
+SQ = dict(nb=NB, ib=32, tree="plasma", param=48, kernels="hybrid")
 
 
 def _first_column_oracle(A0, b0):
