@@ -120,6 +120,28 @@ def timed(fn, steps, warmup, torch, T):
     return (t1 - t0) / steps * 1e3, kern_ms / max(launches, 1), launches / steps
 
 
+def cold_cache_timing(np, torch, T, run_once, steps, flush_bytes=1 << 30):
+    """Executor launch time after the caches beyond the CUs have been
+    flushed: before each call a device buffer of flush_bytes (four times the
+    256 MB Infinity Cache, and far larger than the L2s) is overwritten and
+    the device synchronised; the call's executor launch is then timed with
+    the library's HIP events, as in timed().  (The call's own copy of A into
+    its workspace still runs first and leaves its tail cached.)"""
+    buf = torch.empty(flush_bytes // 4, dtype=torch.int32, device="cuda")
+    ms = []
+    for _ in range(steps):
+        buf.fill_(1)
+        torch.cuda.synchronize()
+        T.debug_timing(True)
+        run_once()
+        torch.cuda.synchronize()
+        k, nl = T.debug_timing_read()
+        T.debug_timing(False)
+        ms.append(k / max(nl, 1))
+    del buf
+    return {"executor_ms": float(np.median(ms)), "executor_ms_all": ms, "flush_bytes": flush_bytes}
+
+
 def recorded_traffic(record, workload):
     """HBM bytes per executor launch from a committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE measurement (profiles/traffic_*.json), or None when the
@@ -386,6 +408,10 @@ def run_square(args, np, torch, T, synth):
                        "equal_fp64_error": bool(be <= 50 * EPS and int(info.item()) == 0)}
             if dt == "f64" and fp64 is None:
                 fp64 = {"ms": ms, "kms": kms, "be": be, "info": int(info.item())}
+                if args.cold_steps > 0:
+                    fp64["cold"] = cold_cache_timing(np, torch, T, lambda: T.lstsq(A, b, o, X=X, work=w, info=info),
+                                                     args.cold_steps)
+                    log("cold caches: executor %.2f ms (warm %.2f ms)" % (fp64["cold"]["executor_ms"], kms))
                 if not args.no_gamma_ub:
                     gub = gamma_ub(T, torch, np, n, n, 1, o, lambda: T.lstsq(A, b, o, X=X, work=w, info=info),
                                    tree, param, fam)
@@ -409,6 +435,8 @@ def run_square(args, np, torch, T, synth):
                      "n": n, "nb": nb, "ib": ib, "tree": tree, "param": param, "kernels": kernels,
                      "kappas": args.kappas, "precision": "plain FP64"})
     out["executor_ms"] = fp64["kms"]
+    if "cold" in fp64:
+        out["cold_cache"] = fp64["cold"]
     out["ls_backward_error"] = fp64["be"]
     out["per_kappa"] = per_kappa
     out["mixed_summary"] = {
@@ -618,6 +646,8 @@ def main():
     ap.add_argument("--square-param", type=int, default=48)
     ap.add_argument("--square-kernels", default="hybrid")
     ap.add_argument("--kappas", type=float, nargs="*", default=[1e2, 1e5, 1e8])
+    ap.add_argument("--cold-steps", type=int, default=3,
+                    help="FP64 square solves timed after flushing the caches (0: none)")
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--nb", type=int, default=256)
     ap.add_argument("--ib", type=int, default=32)
