@@ -39,16 +39,31 @@ enum LoadMode { LD_FULL = 0, LD_LOWER = 1, LD_DIAG = 2 };
 
 // dst = tile (rows x cols valid) of src; LD_LOWER zeroes the strict upper
 // triangle; LD_DIAG also puts ones on the padded part of the diagonal.
+// Every load of the thread is issued before its first LDS store (clamped
+// addresses, masked values), so the tile costs one memory latency rather
+// than one per element.
 template <int NB>
 __device__ __forceinline__ void load_tile(const double *__restrict__ src, int64_t ld, int rows, int cols,
                                           double *dst, int mode) {
   constexpr int LD = CholSmem<NB>::LD;
-  for (int idx = threadIdx.x; idx < NB * NB; idx += CT) {
+  constexpr int PER = NB * NB / CT;
+  static_assert(PER * CT == NB * NB, "a tile splits evenly over the threads");
+  double v[PER];
+#pragma unroll
+  for (int it = 0; it < PER; it++) {
+    const int idx = threadIdx.x + it * CT;
     const int r = idx % NB, c = idx / NB;
-    double v = 0.0;
-    if (r < rows && c < cols && (mode == LD_FULL || r >= c)) v = src[(int64_t)c * ld + r];
-    if (mode == LD_DIAG && r == c && (r >= rows || c >= cols)) v = 1.0;
-    dst[c * LD + r] = v;
+    const bool in = r < rows && c < cols && (mode == LD_FULL || r >= c);
+    const double x = src[(int64_t)(in ? c : 0) * ld + (in ? r : 0)];
+    v[it] = in ? x : 0.0;
+  }
+#pragma unroll
+  for (int it = 0; it < PER; it++) {
+    const int idx = threadIdx.x + it * CT;
+    const int r = idx % NB, c = idx / NB;
+    double x = v[it];
+    if (mode == LD_DIAG && r == c && (r >= rows || c >= cols)) x = 1.0;
+    dst[c * LD + r] = x;
   }
 }
 
