@@ -217,7 +217,7 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
  * Many independent least-squares problems min ||A_x X_x - B_x||, each with
  * its own m_x >= n_x (ragged), nrhs right-hand sides each, in ONE executor
  * launch: the task graphs of all problems form one graph with one ready
- * queue ordered by critical-path length (bottom level) across problems.
+ * queue, in the ready order opts.priority selects over the whole graph.
  * Host arrays of sizes and of device pointers; the matrices are device
  * memory, column-major, and are not modified.  Tile size nb/ib come from
  * opts and are shared by the batch; opts.tree = TQR_AUTO picks per problem
@@ -225,7 +225,10 @@ int tqr_lstsq(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, 
  * among FlatTree, BinaryTree, Fibonacci, Greedy and GrASAP, else every
  * problem uses opts.tree.  With opts.update_dtype != TQR_F64 each problem
  * is refined in FP64 by the semi-normal equations (see tqr_refine_report);
- * the reports of all problems are at the start of `work`, one
+ * unless the stream is being captured, the reports are read back after
+ * each test (the call then synchronises the stream) and no step is
+ * enqueued once every problem has converged; the reports of all problems
+ * are at the start of `work`, one
  * tqr_refine_report per problem, contiguous.  info: NULL or a device array
  * of count int32 (meaning as for tqr_lstsq).  Arguments: -1 count < 1,
  * -2 bad m / n, -4 nrhs < 1, -5 bad A / lda, -7 bad B / ldb, -9 bad X / ldx,

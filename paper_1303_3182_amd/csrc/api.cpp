@@ -1330,10 +1330,26 @@ int tqr_lstsq_batched(int32_t count, const int64_t *m, const int64_t *n, int64_t
     if (copy_batch(dcp + 2 * count, count, nmax * nrhs, stream) != hipSuccess) return TQR_E_HIP;
     const double tol = r.refine_tol > 0.0 ? r.refine_tol : 16.0 * 2.220446049250313e-16;
     if (refine_fro(dref, none, count, stream) != hipSuccess) return TQR_E_HIP;
+    // Unless the stream is being captured, the reports are read back after
+    // each test and no step is enqueued once every problem has converged
+    // (under capture every step is enqueued; converged problems' kernels
+    // return at once).
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool poll = hipStreamIsCapturing(stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone;
+    std::vector<tqr_refine_report> host(poll ? count : 0);
     for (int it = 0; it <= r.max_refine; it++) {
       if (refine_residual(dref, none, count, mmax, nmax, stream) != hipSuccess) return TQR_E_HIP;
       if (refine_check(dref, none, count, tol, it, stream) != hipSuccess) return TQR_E_HIP;
       if (it == r.max_refine) break;
+      if (poll) {
+        if (hipMemcpyAsync(host.data(), reports, (size_t)count * sizeof(tqr_refine_report), hipMemcpyDeviceToHost,
+                           stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+          return TQR_E_HIP;
+        bool all = true;
+        for (int x = 0; x < count && all; x++) all = host[x].done != 0;
+        if (all) break;
+      }
       rc = launch_batch(*bps, r, count, ctl, reinterpret_cast<const Problem *>(w + L.probs_s), info, nullptr,
                         dev, stream, L.state_bytes);
       if (rc) return rc;
