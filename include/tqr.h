@@ -460,7 +460,9 @@ void tqr_debug_timing(int32_t enable);
 int tqr_debug_timing_read(double *ms_total, int64_t *launches);
 
 /* Debug only: the executor's task table for a plan (kind 0 factor, 1 apply
- * with nrhs columns, 2 solve, 3 the least-squares graph of tqr_lstsq) as 8
+ * with nrhs columns, 2 solve, 3 the least-squares graph of tqr_lstsq; 6 the
+ * Cholesky inversion of order m = n with tile size o->nb and variant
+ * o->param, its tasks' i, piv, k, j being the tile indices i, i, k, j) as 8
  * int32 per task: kind, i, piv, k, j,
  * stripe, number of successors, number of predecessors.  Returns the task
  * count (tasks written only if cap >= count). */

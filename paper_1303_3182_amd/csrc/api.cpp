@@ -1956,14 +1956,36 @@ void tqr_debug_trace(int64_t *buf, int64_t cap) {
   g_trace_cap = buf ? cap : 0;
 }
 
-int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *tasks,
-                    int64_t cap) {
+}  // extern "C"
+
+namespace {
+// The plan the debug exports describe: a QR plan (kinds 0-5), or with kind
+// 6 the Cholesky inversion of order m = n, tile size o->nb and variant
+// o->param.
+int debug_key(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, PlanKey *key) {
   if (m < 1 || n < 1 || n > m) return -1;
+  if (kind == PK_CHOLINV) {
+    if (m != n || !o || !cholinv_nb_supported(o->nb) || o->param < 0 || o->param > 3) return -5;
+    *key = cholinv_key(n, o->nb, o->param);
+    return TQR_OK;
+  }
   if (kind < PK_FACTOR || kind > PK_SNE) return -4;
   Resolved r;
-  int rc = resolve(o, &r, m, n);
+  const int rc = resolve(o, &r, m, n);
   if (rc) return rc;
-  auto hp = host_plan(make_key(kind, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), kind == PK_FACTOR ? 0 : nrhs, r));
+  *key = make_key(kind, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), kind == PK_FACTOR ? 0 : nrhs, r);
+  return TQR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *tasks,
+                    int64_t cap) {
+  PlanKey key{};
+  const int rc = debug_key(m, n, nrhs, kind, o, &key);
+  if (rc) return rc;
+  auto hp = host_plan(key);
   const int64_t nt = (int64_t)hp->g.tasks.size();
   if (tasks && cap >= nt)
     for (int64_t t = 0; t < nt; t++) {
@@ -1983,12 +2005,10 @@ int tqr_debug_graph(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_
 
 int tqr_debug_succ(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *off,
                    int32_t *succ, int64_t cap) {
-  if (m < 1 || n < 1 || n > m) return -1;
-  if (kind < PK_FACTOR || kind > PK_SNE) return -4;
-  Resolved r;
-  int rc = resolve(o, &r, m, n);
+  PlanKey key{};
+  const int rc = debug_key(m, n, nrhs, kind, o, &key);
   if (rc) return rc;
-  auto hp = host_plan(make_key(kind, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), kind == PK_FACTOR ? 0 : nrhs, r));
+  auto hp = host_plan(key);
   if ((int64_t)hp->g.succ.size() > cap) return -1;
   std::copy(hp->g.succ_off.begin(), hp->g.succ_off.end(), off);
   std::copy(hp->g.succ.begin(), hp->g.succ.end(), succ);
@@ -1997,12 +2017,10 @@ int tqr_debug_succ(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_o
 
 int tqr_debug_ready(int64_t m, int64_t n, int64_t nrhs, int32_t kind, const tqr_opts *o, int32_t *ready,
                     int64_t cap) {
-  if (m < 1 || n < 1 || n > m) return -1;
-  if (kind < PK_FACTOR || kind > PK_SNE) return -4;
-  Resolved r;
-  int rc = resolve(o, &r, m, n);
+  PlanKey key{};
+  const int rc = debug_key(m, n, nrhs, kind, o, &key);
   if (rc) return rc;
-  auto hp = host_plan(make_key(kind, (int)cdiv(m, r.nb), (int)cdiv(n, r.nb), kind == PK_FACTOR ? 0 : nrhs, r));
+  auto hp = host_plan(key);
   const Graph &g = hp->g;
   if ((int64_t)g.ready0.size() > cap) return -1;
   std::copy(g.ready0.begin(), g.ready0.end(), ready);

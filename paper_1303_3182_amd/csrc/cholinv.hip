@@ -123,68 +123,112 @@ __device__ __forceinline__ void product(const CholSmem<NB> &sm, double alpha, do
     }
 }
 
-// Cholesky factor of the tile in Z (lower, in place), right-looking, one
-// column per step.  A non-positive (or NaN) pivot records the 1-based
-// global index base + c + 1 of the first such column in *notpd.
+// The three diagonal-tile kernels (Cholesky factor, triangular solve,
+// triangular inverse) run in one wave, lane r holding row r of the tile in
+// registers (loops unrolled, so the row is a register array): the factor's
+// columns are broadcast with readlane, a static triangle with LDS broadcast
+// reads.  No workgroup barrier inside; each performs the same operations in
+// the same order as the column-by-column formulation in its comment.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Cholesky factor of the tile in Z (lower, in place), right-looking: for
+// each column c, L(c,c) = sqrt(A(c,c)), L(r,c) = A(r,c) / L(c,c) (r > c),
+// A(r,s) -= L(r,c) L(s,c) (r >= s > c).  A non-positive (or NaN) pivot
+// records the 1-based global index base + c + 1 of the first such column
+// in *notpd.
 template <int NB>
 __device__ __forceinline__ void potrf_lds(CholSmem<NB> &sm, int base, int32_t *notpd) {
   constexpr int LD = CholSmem<NB>::LD;
-  double *Z = sm.Z;
-  for (int c = 0; c < NB; c++) {
-    __syncthreads();  // the previous column's trailing update is complete
-    const double d = Z[c * LD + c];
-    const bool ok = d > 0.0;
-    const double piv = ok ? sqrt(d) : __builtin_nan("");
-    if (!ok && threadIdx.x == 0) atomicMin(notpd, base + c + 1);
-    __syncthreads();  // every thread has read the pivot
-    if (threadIdx.x < NB && (int)threadIdx.x > c) Z[c * LD + threadIdx.x] /= piv;
-    if (threadIdx.x == 0) Z[c * LD + c] = piv;
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < NB * NB; idx += CT) {
-      const int r = idx % NB, s = idx / NB;
-      if (s > c && r >= s) Z[s * LD + r] = fma(-Z[c * LD + r], Z[c * LD + s], Z[s * LD + r]);
+  __syncthreads();  // the tile is in Z
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x;
+    const int rr = r < NB ? r : 0;  // lanes past the tile read row 0 and write nothing
+    double a[NB];
+#pragma unroll
+    for (int s = 0; s < NB; s++) a[s] = sm.Z[s * LD + rr];
+#pragma unroll
+    for (int c = 0; c < NB; c++) {
+      const double d = readlane_d(a[c], c);
+      const bool ok = d > 0.0;
+      const double piv = ok ? sqrt(d) : __builtin_nan("");
+      if (!ok && r == 0) atomicMin(notpd, base + c + 1);
+      a[c] = (r > c) ? a[c] / piv : (r == c ? piv : a[c]);
+#pragma unroll
+      for (int s = c + 1; s < NB; s++) {
+        const double lsc = readlane_d(a[c], s);
+        if (r >= s) a[s] = fma(-a[c], lsc, a[s]);
+      }
+    }
+    if (r < NB) {
+#pragma unroll
+      for (int s = 0; s < NB; s++) sm.Z[s * LD + r] = a[s];
     }
   }
   __syncthreads();
 }
 
-// Z <- Z L^{-T} with L (lower) in X: column c of the result is
-// (Z(:,c) - sum_{k<c} result(:,k) L(c,k)) / L(c,c), right-looking.
+// Z <- Z L^{-T} with L (lower) in X, row by row: for each column c,
+// Z(r,c) /= L(c,c), then Z(r,s) -= Z(r,c) L(s,c) for s > c.
 template <int NB>
 __device__ __forceinline__ void trsm_lds(CholSmem<NB> &sm) {
   constexpr int LD = CholSmem<NB>::LD;
-  double *Z = sm.Z;
   const double *L = sm.X;
-  for (int c = 0; c < NB; c++) {
-    if (threadIdx.x < NB) Z[c * LD + threadIdx.x] /= L[c * LD + c];
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < NB * NB; idx += CT) {
-      const int r = idx % NB, s = idx / NB;
-      if (s > c) Z[s * LD + r] = fma(-Z[c * LD + r], L[c * LD + s], Z[s * LD + r]);
+  __syncthreads();  // X and Z are loaded
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x;
+    const int rr = r < NB ? r : 0;
+    double z[NB];
+#pragma unroll
+    for (int s = 0; s < NB; s++) z[s] = sm.Z[s * LD + rr];
+#pragma unroll
+    for (int c = 0; c < NB; c++) {
+      z[c] /= L[c * LD + c];
+#pragma unroll
+      for (int s = c + 1; s < NB; s++) z[s] = fma(-z[c], L[c * LD + s], z[s]);
     }
-    __syncthreads();
+    if (r < NB) {
+#pragma unroll
+      for (int s = 0; s < NB; s++) sm.Z[s * LD + r] = z[s];
+    }
   }
+  __syncthreads();
 }
 
 // Z <- L^{-1} for L (lower) in Z, in place, from the last column: W(c,c) =
-// 1/L(c,c), W(r,c) = -(sum_{c<k<=r} W(r,k) L(k,c)) W(c,c), r > c.
+// 1/L(c,c), W(r,c) = -(sum_{c<k<=r} W(r,k) L(k,c)) W(c,c), r > c.  Row r of
+// W stays in registers until every column is done, so L is read intact.
 template <int NB>
 __device__ __forceinline__ void trtri_lds(CholSmem<NB> &sm) {
   constexpr int LD = CholSmem<NB>::LD;
-  double *Z = sm.Z;
-  const int r = threadIdx.x;
-  for (int c = NB - 1; c >= 0; c--) {
-    const double wcc = 1.0 / Z[c * LD + c];
-    double v = 0.0;
-    if (r < NB && r > c) {
-      for (int k = c + 1; k <= r; k++) v = fma(Z[k * LD + r], Z[c * LD + k], v);
+  __syncthreads();  // the tile is in Z
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x;
+    const int rr = r < NB ? r : 0;
+    double w[NB];
+#pragma unroll
+    for (int c = 0; c < NB; c++) w[c] = sm.Z[c * LD + rr];  // L's upper part (r < c) is kept
+#pragma unroll
+    for (int c = NB - 1; c >= 0; c--) {
+      const double wcc = 1.0 / sm.Z[c * LD + c];
+      double v = 0.0;
+#pragma unroll
+      for (int k = c + 1; k < NB; k++)
+        if (k <= r) v = fma(w[k], sm.Z[c * LD + k], v);
       v = -v * wcc;
+      w[c] = (r > c) ? v : (r == c ? wcc : w[c]);
     }
-    __syncthreads();  // column c of L read by every thread
-    if (r < NB && r > c) Z[c * LD + r] = v;
-    if (r == c) Z[c * LD + c] = wcc;
-    __syncthreads();
+    // (one wave: every lane's reads of L are done before these writes)
+    if (r < NB) {
+#pragma unroll
+      for (int c = 0; c < NB; c++) sm.Z[c * LD + r] = w[c];
+    }
   }
+  __syncthreads();
 }
 
 template <int NB>
