@@ -57,22 +57,35 @@ template <int NB>
 struct ZSmem {
   static constexpr int LD = NB + 1;
   static constexpr int CW = 32;  // target columns per chunk of the update kernels
-  static constexpr int YC = (NB > 2 * CW) ? NB : 2 * CW;
   cplx X[NB * LD];               // panel: the tile (GEQRT, zeroed tile); updates: the reflectors
-  cplx Y[YC * LD];               // panel: the pivot triangle; updates: target chunks (two of CW columns)
+  cplx Y[NB * LD];               // panel: the pivot triangle
   cplx tau[NB];
   double red[ZT / 64];
   int task;
 };
 
-template <int NB>
+// NB x NCOL block of src (rows x cols valid, zero elsewhere) to dst.  Every
+// load of the thread is issued before its first LDS store (clamped
+// addresses, masked values), so the block costs one memory latency rather
+// than one per element.
+template <int NB, int NCOL>
 __device__ __forceinline__ void zload(const cplx *__restrict__ src, int64_t ld, int rows, int cols, cplx *dst,
-                                      int ldd, int ncol_alloc) {
-  for (int idx = threadIdx.x; idx < NB * ncol_alloc; idx += ZT) {
+                                      int ldd) {
+  constexpr int PER = NB * NCOL / ZT;
+  static_assert(PER * ZT == NB * NCOL, "a block splits evenly over the threads");
+  cplx v[PER];
+#pragma unroll
+  for (int it = 0; it < PER; it++) {
+    const int idx = threadIdx.x + it * ZT;
     const int r = idx % NB, c = idx / NB;
-    cplx v{0.0, 0.0};
-    if (r < rows && c < cols) v = src[(int64_t)c * ld + r];
-    dst[c * ldd + r] = v;
+    const bool in = r < rows && c < cols;
+    const cplx x = src[(int64_t)(in ? c : 0) * ld + (in ? r : 0)];
+    v[it] = in ? x : cplx{0.0, 0.0};
+  }
+#pragma unroll
+  for (int it = 0; it < PER; it++) {
+    const int idx = threadIdx.x + it * ZT;
+    dst[(idx / NB) * ldd + idx % NB] = v[it];
   }
 }
 
@@ -177,37 +190,65 @@ __device__ __forceinline__ void zpanel(ZSmem<NB> &sm, int rows, int ncols) {
 }
 
 // ---------------------------------------------------------- update kernels
-// Q^H applied to a chunk of CW target columns held in LDS: MODE 0 (UNMQR):
-// C2 only, reflector r = [1 at row r; X rows r+1..vrows-1 of column r];
-// MODE 1 (TTMQR) / 2 (TSMQR): [C1; C2], reflector r = [1 at C1's row r;
-// X rows 0..r (TT) or 0..vrows-1 (TS) of column r] applied to C2's rows.
+// Applies the nref reflectors of a tile (in LDS, X and tau) to a chunk of
+// at most CW target columns (MODE 0: C2 <- H^H C2 with unit lower V; 1 / 2:
+// [C1; C2] <- H^H [C1; C2] with V2 upper triangular / full), one reflector
+// at a time, with the target chunk in registers: lane g of the
+// G lanes of column c holds rows g, g + G, ... of that column of C2 (and of
+// C1), loaded from and stored to global memory once per chunk; the
+// reflectors stay in LDS (read-only; the G lanes of a row read the same
+// address across the wave's columns).  Row r's identity term is taken by
+// the lane whose row index equals r, so no register is indexed at run time.
 template <int NB, int MODE>
-__device__ __forceinline__ void zapply_chunk(ZSmem<NB> &sm, cplx *C1, cplx *C2, int vrows, int nref, int ncc) {
+__device__ __forceinline__ void zapply_regs(ZSmem<NB> &sm, cplx *C1g, cplx *C2g, int64_t ld, int vrows, int nref,
+                                            int ncc) {
   constexpr int LD = ZSmem<NB>::LD;
   constexpr int CW = ZSmem<NB>::CW;
-  constexpr int G = ZT / CW;  // 8 lanes per column
+  constexpr int G = ZT / CW;   // lanes per column
+  constexpr int NK = NB / G;   // rows per lane
   const int c = threadIdx.x / G, g = threadIdx.x % G;
+  const bool col = c < ncc;
+  cplx c2[NK], c1[NK];
+#pragma unroll
+  for (int k = 0; k < NK; k++) {
+    const int q = g + G * k;
+    const bool in2 = col && q < vrows;
+    const cplx x2 = C2g[(int64_t)(col ? c : 0) * ld + (in2 ? q : 0)];
+    c2[k] = in2 ? x2 : cplx{0.0, 0.0};
+    if (MODE != 0) {
+      const cplx x1 = C1g[(int64_t)(col ? c : 0) * ld + q];
+      c1[k] = col ? x1 : cplx{0.0, 0.0};
+    }
+  }
   for (int r = 0; r < nref; r++) {
     const int r0 = (MODE == 0) ? r + 1 : 0;
     const int r1 = (MODE == 0) ? vrows : (MODE == 1 ? min(r + 1, vrows) : vrows);
     cplx w{0.0, 0.0};
-    if (c < ncc) {
-      for (int q = r0 + g; q < r1; q += G) w = cfma_conj(sm.X[r * LD + q], C2[c * LD + q], w);
-      if (g == 0) w = cadd(w, (MODE == 0) ? C2[c * LD + r] : C1[c * LD + r]);
+#pragma unroll
+    for (int k = 0; k < NK; k++) {
+      const int q = g + G * k;
+      if (q >= r0 && q < r1) w = cfma_conj(sm.X[r * LD + q], c2[k], w);
+      if (q == r) w = cadd(w, (MODE == 0) ? c2[k] : c1[k]);  // the identity part of the reflector
     }
     w = group_sum_c<G>(w);
-    if (c < ncc) {
-      const cplx f = cmul(conjc(sm.tau[r]), w);
-      for (int q = r0 + g; q < r1; q += G) C2[c * LD + q] = cfms(f, sm.X[r * LD + q], C2[c * LD + q]);
-      if (g == 0) {
+    const cplx f = cmul(conjc(sm.tau[r]), w);
+#pragma unroll
+    for (int k = 0; k < NK; k++) {
+      const int q = g + G * k;
+      if (q >= r0 && q < r1) c2[k] = cfms(f, sm.X[r * LD + q], c2[k]);
+      if (q == r) {
         if (MODE == 0)
-          C2[c * LD + r] = csub(C2[c * LD + r], f);
+          c2[k] = csub(c2[k], f);
         else
-          C1[c * LD + r] = csub(C1[c * LD + r], f);
+          c1[k] = csub(c1[k], f);
       }
     }
-    __syncthreads();  // (each column's entries belong to one lane group; the
-                      // barrier keeps the reflector loop in step for LDS reuse)
+  }
+#pragma unroll
+  for (int k = 0; k < NK; k++) {
+    const int q = g + G * k;
+    if (col && q < vrows) C2g[(int64_t)c * ld + q] = c2[k];
+    if (MODE != 0 && col) C1g[(int64_t)c * ld + q] = c1[k];
   }
 }
 
@@ -226,8 +267,8 @@ __device__ __forceinline__ void run_ztask(const Problem &p, const Task &t, ZSmem
   if (kind == K_GEQRT || kind == K_TTQRT || kind == K_TSQRT) {
     const int ncols = (int)min((int64_t)NB, p.n - (int64_t)t.k * NB);
     const int rows = rowsOf(t.i);
-    zload<NB>(tile(t.i, t.k), lda, rows, ncols, sm.X, LD, NB);
-    if (kind != K_GEQRT) zload<NB>(tile(t.piv, t.k), lda, NB, ncols, sm.Y, LD, NB);
+    zload<NB, NB>(tile(t.i, t.k), lda, rows, ncols, sm.X, LD);
+    if (kind != K_GEQRT) zload<NB, NB>(tile(t.piv, t.k), lda, NB, ncols, sm.Y, LD);
     __syncthreads();
     if (kind == K_GEQRT) {
       zpanel<NB, 0>(sm, rows, ncols);
@@ -264,38 +305,35 @@ __device__ __forceinline__ void run_ztask(const Problem &p, const Task &t, ZSmem
   // the reflectors, masked to their structure
   {
     const cplx *V = tile(t.i, t.k);
-    for (int idx = threadIdx.x; idx < NB * NB; idx += ZT) {
+    constexpr int PER = NB * NB / ZT;
+    cplx v[PER];
+#pragma unroll
+    for (int it = 0; it < PER; it++) {  // every load before the first LDS store
+      const int idx = threadIdx.x + it * ZT;
       const int r = idx % NB, c = idx / NB;
-      cplx v{0.0, 0.0};
-      const bool in = r < vrows && c < nref;
-      if (in && ((mode == 0 && r > c) || (mode == 1 && r <= c) || mode == 2)) v = V[(int64_t)c * lda + r];
-      sm.X[c * LD + r] = v;
+      const bool in = r < vrows && c < nref && ((mode == 0 && r > c) || (mode == 1 && r <= c) || mode == 2);
+      const cplx x = V[(int64_t)(in ? c : 0) * lda + (in ? r : 0)];
+      v[it] = in ? x : cplx{0.0, 0.0};
+    }
+#pragma unroll
+    for (int it = 0; it < PER; it++) {
+      const int idx = threadIdx.x + it * ZT;
+      sm.X[(idx / NB) * LD + idx % NB] = v[it];
     }
     const cplx *tv = tauOf(t.i, t.k, mode == 0 ? 0 : 1);
     for (int x = threadIdx.x; x < NB; x += ZT) sm.tau[x] = (x < nref) ? tv[x] : cplx{0.0, 0.0};
   }
-  cplx *C1s = sm.Y;            // C1 chunk (rows of the pivot tile)
-  cplx *C2s = sm.Y + CW * LD;  // C2 chunk
+  __syncthreads();  // the reflectors and taus are in LDS
   for (int cs = 0; cs < ncols; cs += CW) {
     const int ncc = min(CW, ncols - cs);
     cplx *C2g = base + (int64_t)cs * ld + (int64_t)t.i * NB;
     cplx *C1g = base + (int64_t)cs * ld + (int64_t)t.piv * NB;
-    __syncthreads();
-    zload<NB>(C2g, ld, vrows, ncc, C2s, LD, CW);
-    if (mode != 0) zload<NB>(C1g, ld, NB, ncc, C1s, LD, CW);
-    __syncthreads();
     if (mode == 0)
-      zapply_chunk<NB, 0>(sm, C1s, C2s, vrows, nref, ncc);
+      zapply_regs<NB, 0>(sm, C1g, C2g, ld, vrows, nref, ncc);
     else if (mode == 1)
-      zapply_chunk<NB, 1>(sm, C1s, C2s, vrows, nref, ncc);
+      zapply_regs<NB, 1>(sm, C1g, C2g, ld, vrows, nref, ncc);
     else
-      zapply_chunk<NB, 2>(sm, C1s, C2s, vrows, nref, ncc);
-    for (int idx = threadIdx.x; idx < NB * CW; idx += ZT) {
-      const int r = idx % NB, c = idx / NB;
-      if (c >= ncc) continue;
-      if (r < vrows) C2g[(int64_t)c * ld + r] = C2s[c * LD + r];
-      if (mode != 0) C1g[(int64_t)c * ld + r] = C1s[c * LD + r];
-    }
+      zapply_regs<NB, 2>(sm, C1g, C2g, ld, vrows, nref, ncc);
   }
 }
 
