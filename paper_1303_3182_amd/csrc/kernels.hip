@@ -146,6 +146,14 @@ struct Smem {
   __device__ double *YL() { return VL[1]; }
 };
 
+// The matrices, T factors and right-hand sides are in device memory and
+// reached through pointers typed in the global address space.  Plain
+// pointers read from the problem table would be generic (flat) to the
+// compiler, and flat accesses also count against the LDS wait counter: every
+// wait for an LDS operand would then wait for each tile load and store in
+// flight as well.
+typedef __attribute__((address_space(1))) double gdouble;
+
 enum { M_UNM = 0, M_TT = 1, M_TS = 2 };
 
 // Columns of a chunk handled by one apply pass: 4 waves x 16 columns.
@@ -156,7 +164,7 @@ constexpr int CHUNK = 64;
 // upper triangular including the diagonal, M_TS full.  Columns past vcols
 // and rows past vrows are zero (no reflector / zero padding).
 template <int NB, int IB, int WC, int MODE>
-__device__ __forceinline__ void stage_v(const double *__restrict__ V, int64_t ldv, int vrows, int vcols,
+__device__ __forceinline__ void stage_v(const gdouble *__restrict__ V, int64_t ldv, int vrows, int vcols,
                                         int b, int rlo, int rhi, double *VLb) {
   constexpr int TPR = (NT / NB) > 0 ? NT / NB : 1;  // threads per row
   constexpr int CPT = IB / TPR;                      // columns per thread
@@ -190,7 +198,7 @@ __device__ __forceinline__ void stage_v(const double *__restrict__ V, int64_t ld
 // moves two rows, no registers).  Only for full tiles with 16-byte aligned
 // columns; the triangular structure is applied when the operands are read.
 template <int NB, int IB, int WC>
-__device__ __forceinline__ void dma_v(const double *__restrict__ V, int64_t ldv, int b, int rlo, int rhi,
+__device__ __forceinline__ void dma_v(const gdouble *__restrict__ V, int64_t ldv, int b, int rlo, int rhi,
                                       double *VLb) {
   constexpr int SEG = 128;
   constexpr int LDV = Smem<NB, IB, WC>::LDV;
@@ -199,8 +207,9 @@ __device__ __forceinline__ void dma_v(const double *__restrict__ V, int64_t ldv,
   const int s0 = rlo / SEG, s1 = (rhi + SEG - 1) / SEG, ns = s1 - s0;
   for (int it = wave; it < IB * ns; it += NT / 64) {
     const int cc = it / ns, seg = s0 + it % ns;
-    const double *gp = V + (int64_t)(b * IB + cc) * ldv + seg * SEG + 2 * lane;
-    __builtin_amdgcn_global_load_lds(gp, (__attribute__((address_space(3))) void *)(VLb + cc * LDV + seg * SEG),
+    const gdouble *gp = V + (int64_t)(b * IB + cc) * ldv + seg * SEG + 2 * lane;
+    __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)gp,
+                                     (__attribute__((address_space(3))) void *)(VLb + cc * LDV + seg * SEG),
                                      16, 0, 0);
   }
 }
@@ -236,9 +245,9 @@ __device__ __forceinline__ double vmask(double v, int row, int col) {
 // with it which MFMAs run and which operands are loaded, is known to the
 // compiler and the loads are scheduled ahead across row blocks.
 template <int NB, int IB, int WC, int MODE, int FB0 = -1, int FB1 = -1>
-__device__ __forceinline__ void apply_chunk(const double *__restrict__ V, int64_t ldv, int vrows,
-                                            int vcols, const double *__restrict__ Tf, double *C1,
-                                            int64_t ldc1, double *C2, int64_t ldc2, int c2rows,
+__device__ __forceinline__ void apply_chunk(const gdouble *__restrict__ V, int64_t ldv, int vrows,
+                                            int vcols, const gdouble *__restrict__ Tf, gdouble *C1,
+                                            int64_t ldc1, gdouble *C2, int64_t ldc2, int c2rows,
                                             int ncols, int b0, int b1, bool prestaged, bool dma,
                                             Smem<NB, IB, WC> &sm) {
   if constexpr (FB0 >= 0) {
@@ -436,9 +445,9 @@ __device__ __forceinline__ void apply_chunk(const double *__restrict__ V, int64_
 enum { P_F32 = 1, P_BF16 = 2 };
 
 template <int NB, int IB, int WC, int MODE, int P>
-__device__ __forceinline__ void apply_chunk_lp(const double *__restrict__ V, int64_t ldv, int vrows,
-                                               int vcols, const double *__restrict__ Tf, double *C1,
-                                               int64_t ldc1, double *C2, int64_t ldc2, int c2rows,
+__device__ __forceinline__ void apply_chunk_lp(const gdouble *__restrict__ V, int64_t ldv, int vrows,
+                                               int vcols, const gdouble *__restrict__ Tf, gdouble *C1,
+                                               int64_t ldc1, gdouble *C2, int64_t ldc2, int c2rows,
                                                int ncols, bool dma, Smem<NB, IB, WC> &sm) {
   constexpr int NRB = NB / 16;
   constexpr int NMB = IB / 16;
@@ -673,8 +682,8 @@ constexpr int panel_slots(int b) {
 // PRU = panel_slots(B) row slots that hold the block's live panel rows
 // (TT: 2 IB + B IB rows, GEQRT: NB - B IB), not the whole tile's padding.
 template <int NB, int IB, int WC, int MODE, int B>
-__device__ __forceinline__ void panel_block(double *Vt, int64_t ldv, int vrows, double *R1,
-                                            int64_t ldr, int ncols, double *Tout,
+__device__ __forceinline__ void panel_block(gdouble *Vt, int64_t ldv, int vrows, gdouble *R1,
+                                            int64_t ldr, int ncols, gdouble *Tout,
                                             Smem<NB, IB, WC> &sm) {
   constexpr int RG = NT / IB;
   constexpr int PRU = panel_slots<NB, IB, MODE>(B);
@@ -898,8 +907,8 @@ __device__ __forceinline__ void panel_block(double *Vt, int64_t ldv, int vrows, 
 // the far columns see few, long MFMA passes instead of one per block.  The
 // block ranges are compile-time constants (see apply_chunk).
 template <int NB, int IB, int WC, int MODE, int B>
-__device__ __forceinline__ void panel_trailing(double *Vt, int64_t ldv, int vrows, double *R1,
-                                               int64_t ldr, int ncols, double *Tout,
+__device__ __forceinline__ void panel_trailing(gdouble *Vt, int64_t ldv, int vrows, gdouble *R1,
+                                               int64_t ldr, int ncols, gdouble *Tout,
                                                Smem<NB, IB, WC> &sm) {
   constexpr int NBLK = NB / IB;
   constexpr int KOUT = (128 / IB) < NBLK ? (128 / IB) : NBLK;  // blocks per outer block
@@ -929,8 +938,8 @@ __device__ __forceinline__ void panel_trailing(double *Vt, int64_t ldv, int vrow
 // Runs inner block b (factorization and trailing update) with b fixed at
 // compile time.
 template <int NB, int IB, int WC, int MODE, int B = 0>
-__device__ __forceinline__ void panel_block_at(int b, double *Vt, int64_t ldv, int vrows, double *R1,
-                                               int64_t ldr, int ncols, double *Tout,
+__device__ __forceinline__ void panel_block_at(int b, gdouble *Vt, int64_t ldv, int vrows, gdouble *R1,
+                                               int64_t ldr, int ncols, gdouble *Tout,
                                                Smem<NB, IB, WC> &sm) {
   if (b == B) {
     panel_block<NB, IB, WC, MODE, B>(Vt, ldv, vrows, R1, ldr, ncols, Tout, sm);
@@ -945,8 +954,8 @@ __device__ __forceinline__ void panel_block_at(int b, double *Vt, int64_t ldv, i
 // ragged last tile column has ncols < NB); the later blocks hold no
 // reflectors and get a zero T.
 template <int NB, int IB, int WC, int MODE>
-__device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, double *R1,
-                                           int64_t ldr, int ncols, double *Tout,
+__device__ __forceinline__ void panel_tile(gdouble *Vt, int64_t ldv, int vrows, gdouble *R1,
+                                           int64_t ldr, int ncols, gdouble *Tout,
                                            Smem<NB, IB, WC> &sm) {
   const int nblk = (ncols + IB - 1) / IB;
   for (int b = 0; b < nblk; b++) panel_block_at<NB, IB, WC, MODE>(b, Vt, ldv, vrows, R1, ldr, ncols, Tout, sm);
@@ -962,8 +971,8 @@ __device__ __forceinline__ void panel_tile(double *Vt, int64_t ldv, int vrows, d
 //              updated on MFMA.  Rows >= nk (past n) are left untouched.
 // Both keep the chunk in registers in the MFMA accumulator layout.
 template <int NB, int IB, int WC>
-__device__ __forceinline__ void gemm_tile(const double *R, int64_t ldr, int nk, const double *X, int64_t ldx,
-                          double *C, int64_t ldc, int crows, int ncols, bool trans, Smem<NB, IB, WC> &sm) {
+__device__ __forceinline__ void gemm_tile(const gdouble *R, int64_t ldr, int nk, const gdouble *X, int64_t ldx,
+                          gdouble *C, int64_t ldc, int crows, int ncols, bool trans, Smem<NB, IB, WC> &sm) {
   constexpr int NRB = NB / 16, RBW = (NRB + 3) / 4, NCB = WC / 16;
   constexpr int LDV = Smem<NB, IB, WC>::LDV, LDW = Smem<NB, IB, WC>::LDW;
   const int tid = opaque_tid(), w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
@@ -1021,7 +1030,7 @@ __device__ __forceinline__ void gemm_tile(const double *R, int64_t ldr, int nk, 
 }
 
 template <int NB, int IB, int WC>
-__device__ __forceinline__ void trsm_tile(const double *R, int64_t ldr, int nk, double *X, int64_t ldx, int ncols,
+__device__ __forceinline__ void trsm_tile(const gdouble *R, int64_t ldr, int nk, gdouble *X, int64_t ldx, int ncols,
                           int row0, int32_t *singular, Smem<NB, IB, WC> &sm) {
   constexpr int NRB = NB / 16, RBW = (NRB + 3) / 4, NCB = WC / 16, NMB = IB / 16;
   constexpr int LDV = Smem<NB, IB, WC>::LDV, LDT = Smem<NB, IB, WC>::LDT, LDW = Smem<NB, IB, WC>::LDW;
@@ -1129,7 +1138,7 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 // column, GV_BT columns per batch, and issues the whole batch's loads
 // (clamped in bounds, so unconditional) before storing any.
 template <int NB>
-__device__ __forceinline__ void stage_cols(const double *__restrict__ src, int64_t ld, int nr, int nc,
+__device__ __forceinline__ void stage_cols(const gdouble *__restrict__ src, int64_t ld, int nr, int nc,
                                            double *dst) {
   constexpr int U = (NB + 63) / 64;
   constexpr int NW = NT / 64;
@@ -1163,7 +1172,7 @@ __device__ __forceinline__ void stage_cols(const double *__restrict__ src, int64
 // solve's serial per-column loops; the diagonal's reciprocals are taken
 // while a block is staged, so the chain multiplies instead of dividing.
 template <int NB, int IB, int WC>
-__device__ __forceinline__ void trsm_waves(const double *R, int64_t ldr, int nk, double *X, int64_t ldx,
+__device__ __forceinline__ void trsm_waves(const gdouble *R, int64_t ldr, int nk, gdouble *X, int64_t ldx,
                                            int ncols, int row0, int32_t *singular, Smem<NB, IB, WC> &sm) {
   constexpr int U = (NB + 63) / 64;  // row groups of 64
   constexpr int CB = NB < 64 ? NB : 64;
@@ -1255,8 +1264,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 constexpr int GV_COLS = 8;
 constexpr int GV_BT = 8;
 template <int NB, int IB, int WC>
-__device__ __forceinline__ void gemv_tile(const double *R, int64_t ldr, int nk, const double *X, int64_t ldx,
-                                          double *C, int64_t ldc, int crows, int ncols, bool trans,
+__device__ __forceinline__ void gemv_tile(const gdouble *R, int64_t ldr, int nk, const gdouble *X, int64_t ldx,
+                                          gdouble *C, int64_t ldc, int crows, int ncols, bool trans,
                                           Smem<NB, IB, WC> &sm) {
   constexpr int U = (NB + 63) / 64;
   constexpr int NW = NT / 64;
@@ -1345,7 +1354,7 @@ __device__ __forceinline__ void gemv_tile(const double *R, int64_t ldr, int nk, 
 // R's columns contiguous in LDS exactly as the backward solve stages them
 // (with the diagonal's reciprocals, as there).
 template <int NB, int IB, int WC>
-__device__ __forceinline__ void trsmt_waves(const double *R, int64_t ldr, int nk, double *X, int64_t ldx,
+__device__ __forceinline__ void trsmt_waves(const gdouble *R, int64_t ldr, int nk, gdouble *X, int64_t ldx,
                                             int ncols, int row0, int32_t *singular, Smem<NB, IB, WC> &sm) {
   constexpr int U = (NB + 63) / 64;
   constexpr int CB = NB < 64 ? NB : 64;
@@ -1415,15 +1424,18 @@ template <int NB, int IB, int WC>
 __device__ __forceinline__ void run_task(const Problem &a, const Task &t, Smem<NB, IB, WC> &sm) {
   if (a.skip && *a.skip) return;
   const int64_t lda = a.lda;
-  auto tileA = [&](int i, int j) { return a.A + (int64_t)j * NB * lda + (int64_t)i * NB; };
+  gdouble *const gA = (gdouble *)a.A;
+  gdouble *const gB = (gdouble *)a.B;
+  gdouble *const gTf = (gdouble *)a.Tf;
+  auto tileA = [&](int i, int j) { return gA + (int64_t)j * NB * lda + (int64_t)i * NB; };
   auto rowsOf = [&](int i) { return (int)min((int64_t)NB, a.m - (int64_t)i * NB); };
   auto Tof = [&](int i, int k, int which) {
-    return a.Tf + (((int64_t)i * a.q + k) * 2 + which) * (int64_t)IB * NB;
+    return gTf + (((int64_t)i * a.q + k) * 2 + which) * (int64_t)IB * NB;
   };
   const int kind = t.kind;
   if (kind == K_GEQRT || kind == K_TTQRT || kind == K_TSQRT) {
     const int ncols = (int)min((int64_t)NB, a.n - (int64_t)t.k * NB);
-    double *Vt = tileA(t.i, t.k);
+    gdouble *Vt = tileA(t.i, t.k);
     if (kind == K_GEQRT)
       panel_tile<NB, IB, WC, M_UNM>(Vt, lda, rowsOf(t.i), nullptr, 0, ncols, Tof(t.i, t.k, 0), sm);
     else if (kind == K_TTQRT)
@@ -1441,7 +1453,7 @@ __device__ __forceinline__ void run_task(const Problem &a, const Task &t, Smem<N
     const int ncols = (int)min((int64_t)NB, a.nrhs - (int64_t)jb * NB);
     const int cbeg = t.stripe * a.sw_b;
     const int cend = imin(ncols, cbeg + a.sw_b);
-    double *Bc = a.B + (int64_t)jb * NB * a.ldb;
+    gdouble *Bc = gB + (int64_t)jb * NB * a.ldb;
     for (int cs = cbeg; cs < cend; cs += WC) {
       const int nc = imin(WC, cend - cs);
       if (kind == K_TRSM && nc <= 2 * (NT / 64))
@@ -1471,19 +1483,19 @@ __device__ __forceinline__ void run_task(const Problem &a, const Task &t, Smem<N
     return;
   }
   // update kinds: target column j (A if j < q, else B)
-  double *base;
+  gdouble *base;
   int64_t ld;
   int ncols;
   if (t.j < a.q) {
-    base = a.A + (int64_t)t.j * NB * lda;
+    base = gA + (int64_t)t.j * NB * lda;
     ld = lda;
     ncols = (int)min((int64_t)NB, a.n - (int64_t)t.j * NB);
   } else {
-    base = a.B + (int64_t)(t.j - a.q) * NB * a.ldb;
+    base = gB + (int64_t)(t.j - a.q) * NB * a.ldb;
     ld = a.ldb;
     ncols = (int)min((int64_t)NB, a.nrhs - (int64_t)(t.j - a.q) * NB);
   }
-  const double *V = tileA(t.i, t.k);
+  const gdouble *V = tileA(t.i, t.k);
   const int vrows = rowsOf(t.i);
   const int vcols = (int)min((int64_t)NB, a.n - (int64_t)t.k * NB);
   const int sw = (t.j < a.q) ? a.sw : a.sw_b;
@@ -1493,9 +1505,9 @@ __device__ __forceinline__ void run_task(const Problem &a, const Task &t, Smem<N
   const int lp = (t.j < a.q) ? a.update_dtype : 0;  // B's columns always in FP64
   for (int cs = cbeg; cs < cend; cs += CHUNK) {
     const int nc = imin(CHUNK, cend - cs);
-    double *C2 = base + (int64_t)cs * ld + (int64_t)t.i * NB;
+    gdouble *C2 = base + (int64_t)cs * ld + (int64_t)t.i * NB;
     if (lp != 0) {
-      double *C1 = base + (int64_t)cs * ld + (int64_t)t.piv * NB;
+      gdouble *C1 = base + (int64_t)cs * ld + (int64_t)t.piv * NB;
       if (lp == P_F32) {
         if (kind == K_UNMQR)
           apply_chunk_lp<NB, IB, WC, M_UNM, P_F32>(V, lda, vrows, vcols, Tof(t.i, t.k, 0), nullptr, 0, C2, ld,
@@ -1527,7 +1539,7 @@ __device__ __forceinline__ void run_task(const Problem &a, const Task &t, Smem<N
         apply_chunk<NB, IB, WC, M_UNM>(V, lda, vrows, vcols, Tof(t.i, t.k, 0), nullptr, 0, C2, ld, vrows, nc, 0,
                                        nblk, false, dma, sm);
       } else {
-        double *C1 = base + (int64_t)cs * ld + (int64_t)t.piv * NB;
+        gdouble *C1 = base + (int64_t)cs * ld + (int64_t)t.piv * NB;
         if (kind == K_TTMQR)
           apply_chunk<NB, IB, WC, M_TT>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld, vrows, nc, 0,
                                         nblk, false, dma, sm);
@@ -1543,7 +1555,7 @@ __device__ __forceinline__ void run_task(const Problem &a, const Task &t, Smem<N
       apply_chunk<NB, IB, WC, M_UNM, 0, NB / IB>(V, lda, vrows, vcols, Tof(t.i, t.k, 0), nullptr, 0, C2, ld,
                                              vrows, nc, 0, NB / IB, false, dma, sm);
     } else {
-      double *C1 = base + (int64_t)cs * ld + (int64_t)t.piv * NB;
+      gdouble *C1 = base + (int64_t)cs * ld + (int64_t)t.piv * NB;
       if (kind == K_TTMQR)
         apply_chunk<NB, IB, WC, M_TT, 0, NB / IB>(V, lda, vrows, vcols, Tof(t.i, t.k, 1), C1, ld, C2, ld, vrows,
                                               nc, 0, NB / IB, false, dma, sm);
