@@ -51,7 +51,40 @@ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
   const double r = b.re / b.im, d = b.re * r + b.im;
   return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
 }
-__device__ __forceinline__ cplx shfl_xor_c(cplx v, int m) { return {__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64)}; }
+
+// Lane moves and reductions inside a wave without LDS: DPP within each row
+// of 16 lanes, readlane across rows (a shuffle would go through LDS, with
+// its latency on every step of the chain).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over aligned groups of G lanes (every lane of the wave active): the
+// xor-1, xor-2, xor-4 (and xor-8) butterfly, so each lane of a group gets
+// the same, order-independent sum.
+template <int G>
+__device__ __forceinline__ double group_sum_d(double v) {
+  static_assert(G == 4 || G == 8 || G == 16, "group of 4, 8 or 16 lanes");
+  v += dpp_d<0xB1>(v);                // quad_perm [1,0,3,2]: lane ^ 1
+  v += dpp_d<0x4E>(v);                // quad_perm [2,3,0,1]: lane ^ 2
+  if (G >= 8) v += dpp_d<0x141>(v);   // row_half_mirror: the other quad of the 8
+  if (G == 16) v += dpp_d<0x140>(v);  // row_mirror: the other half of the row
+  return v;
+}
+// Sum over the 64 lanes of the wave, the same value in every lane.
+__device__ __forceinline__ double wave_sum_d(double v) {
+  v = group_sum_d<16>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
 
 template <int NB>
 struct ZSmem {
@@ -104,9 +137,7 @@ __device__ __forceinline__ void zstore(cplx *__restrict__ dst, int64_t ld, int r
 // Sum of v over the G consecutive lanes of a group (G a power of two <= 64).
 template <int G>
 __device__ __forceinline__ cplx group_sum_c(cplx v) {
-#pragma unroll
-  for (int m = 1; m < G; m <<= 1) v = cadd(v, shfl_xor_c(v, m));
-  return v;
+  return {group_sum_d<G>(v.re), group_sum_d<G>(v.im)};
 }
 
 // Reflector of x = [alpha; x2] with ||x2||^2 = s2 (real) and alpha: writes
@@ -147,8 +178,7 @@ __device__ __forceinline__ void zpanel(ZSmem<NB> &sm, int rows, int ncols) {
         const cplx x = sm.X[j * LD + r];
         s = fma(x.re, x.re, fma(x.im, x.im, s));
       }
-#pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+      s = wave_sum_d(s);
       const cplx alpha = (MODE == 0) ? sm.X[j * LD + j] : sm.Y[j * LD + j];
       cplx tau, scale;
       double beta;
@@ -198,7 +228,8 @@ __device__ __forceinline__ void zpanel(ZSmem<NB> &sm, int rows, int ncols) {
 // C1), loaded from and stored to global memory once per chunk; the
 // reflectors stay in LDS (read-only; the G lanes of a row read the same
 // address across the wave's columns).  Row r's identity term is taken by
-// the lane whose row index equals r, so no register is indexed at run time.
+// the lane whose row index equals r, so no register is indexed at run time,
+// and the per-lane row conditions are selects, not branches.
 template <int NB, int MODE>
 __device__ __forceinline__ void zapply_regs(ZSmem<NB> &sm, cplx *C1g, cplx *C2g, int64_t ld, int vrows, int nref,
                                             int ncc) {
@@ -221,27 +252,28 @@ __device__ __forceinline__ void zapply_regs(ZSmem<NB> &sm, cplx *C1g, cplx *C2g,
     }
   }
   for (int r = 0; r < nref; r++) {
-    const int r0 = (MODE == 0) ? r + 1 : 0;
-    const int r1 = (MODE == 0) ? vrows : (MODE == 1 ? min(r + 1, vrows) : vrows);
+    // Reflector r is column r of the staged tile, already zero outside its
+    // rows, and rows past vrows of C2 are zero: no per-row guards (exact,
+    // the masked terms add zeros).  Its unit entry is row r of C2 (MODE 0)
+    // or of C1, taken by the lane that holds that row.
     cplx w{0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < NK; k++) {
       const int q = g + G * k;
-      if (q >= r0 && q < r1) w = cfma_conj(sm.X[r * LD + q], c2[k], w);
-      if (q == r) w = cadd(w, (MODE == 0) ? c2[k] : c1[k]);  // the identity part of the reflector
+      w = cfma_conj(sm.X[r * LD + q], c2[k], w);
+      const cplx id = (MODE == 0) ? c2[k] : c1[k];
+      w = cadd(w, (q == r) ? id : cplx{0.0, 0.0});
     }
     w = group_sum_c<G>(w);
     const cplx f = cmul(conjc(sm.tau[r]), w);
 #pragma unroll
     for (int k = 0; k < NK; k++) {
       const int q = g + G * k;
-      if (q >= r0 && q < r1) c2[k] = cfms(f, sm.X[r * LD + q], c2[k]);
-      if (q == r) {
-        if (MODE == 0)
-          c2[k] = csub(c2[k], f);
-        else
-          c1[k] = csub(c1[k], f);
-      }
+      c2[k] = cfms(f, sm.X[r * LD + q], c2[k]);
+      if (MODE == 0)
+        c2[k] = (q == r) ? csub(c2[k], f) : c2[k];
+      else
+        c1[k] = (q == r) ? csub(c1[k], f) : c1[k];
     }
   }
 #pragma unroll
