@@ -227,9 +227,7 @@ __device__ __forceinline__ void zpanel(ZSmem<NB> &sm, int rows, int ncols) {
 // G lanes of column c holds rows g, g + G, ... of that column of C2 (and of
 // C1), loaded from and stored to global memory once per chunk; the
 // reflectors stay in LDS (read-only; the G lanes of a row read the same
-// address across the wave's columns).  Row r's identity term is taken by
-// the lane whose row index equals r, so no register is indexed at run time,
-// and the per-lane row conditions are selects, not branches.
+// address across the wave's columns).
 template <int NB, int MODE>
 __device__ __forceinline__ void zapply_regs(ZSmem<NB> &sm, cplx *C1g, cplx *C2g, int64_t ld, int vrows, int nref,
                                             int ncc) {
@@ -251,29 +249,31 @@ __device__ __forceinline__ void zapply_regs(ZSmem<NB> &sm, cplx *C1g, cplx *C2g,
       c1[k] = col ? x1 : cplx{0.0, 0.0};
     }
   }
-  for (int r = 0; r < nref; r++) {
-    // Reflector r is column r of the staged tile, already zero outside its
-    // rows, and rows past vrows of C2 are zero: no per-row guards (exact,
-    // the masked terms add zeros).  Its unit entry is row r of C2 (MODE 0)
-    // or of C1, taken by the lane that holds that row.
-    cplx w{0.0, 0.0};
+  // Reflector r = G kr + gr is column r of the staged tile, already zero
+  // outside its rows, and rows past vrows of C2 are zero: no per-row guards
+  // (exact, the masked terms add zeros).  Its unit entry is row r of C2
+  // (MODE 0) or of C1, held by lane gr in slot kr; the slot loop is
+  // unrolled, so that slot is a fixed register and only lane gr selects it.
 #pragma unroll
-    for (int k = 0; k < NK; k++) {
-      const int q = g + G * k;
-      w = cfma_conj(sm.X[r * LD + q], c2[k], w);
-      const cplx id = (MODE == 0) ? c2[k] : c1[k];
-      w = cadd(w, (q == r) ? id : cplx{0.0, 0.0});
-    }
-    w = group_sum_c<G>(w);
-    const cplx f = cmul(conjc(sm.tau[r]), w);
+  for (int kr = 0; kr < NK; kr++) {
+    if (kr * G < nref) {
+      const int gend = min(G, nref - kr * G);
+      for (int gr = 0; gr < gend; gr++) {
+        const int r = kr * G + gr;
+        cplx w{0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < NK; k++) {
-      const int q = g + G * k;
-      c2[k] = cfms(f, sm.X[r * LD + q], c2[k]);
-      if (MODE == 0)
-        c2[k] = (q == r) ? csub(c2[k], f) : c2[k];
-      else
-        c1[k] = (q == r) ? csub(c1[k], f) : c1[k];
+        for (int k = 0; k < NK; k++) w = cfma_conj(sm.X[r * LD + g + G * k], c2[k], w);
+        const cplx id = (MODE == 0) ? c2[kr] : c1[kr];
+        w = cadd(w, (g == gr) ? id : cplx{0.0, 0.0});
+        w = group_sum_c<G>(w);
+        const cplx f = cmul(conjc(sm.tau[r]), w);
+#pragma unroll
+        for (int k = 0; k < NK; k++) c2[k] = cfms(f, sm.X[r * LD + g + G * k], c2[k]);
+        if (MODE == 0)
+          c2[kr] = (g == gr) ? csub(c2[kr], f) : c2[kr];
+        else
+          c1[kr] = (g == gr) ? csub(c1[kr], f) : c1[kr];
+      }
     }
   }
 #pragma unroll
