@@ -23,7 +23,7 @@ namespace tqr {
 
 namespace {
 
-constexpr int ZT = 256;  // threads per workgroup
+constexpr int ZT = 512;  // threads per workgroup: two waves per SIMD
 
 struct cplx {
   double re, im;
@@ -89,7 +89,7 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 template <int NB>
 struct ZSmem {
   static constexpr int LD = NB + 1;
-  static constexpr int CW = 32;  // target columns per chunk of the update kernels
+  static constexpr int CW = NB < 64 ? NB : 64;  // target columns per chunk of the update kernels
   cplx X[NB * LD];               // panel: the tile (GEQRT, zeroed tile); updates: the reflectors
   cplx Y[NB * LD];               // panel: the pivot triangle
   cplx tau[NB];
