@@ -55,11 +55,13 @@ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
 // Lane moves and reductions inside a wave without LDS: DPP within each row
 // of 16 lanes, readlane across rows (a shuffle would go through LDS, with
 // its latency on every step of the chain).
+// (every pattern used reads a lane of the same row, always active, so no
+// fallback value is needed)
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double readlane_d(double v, int lane) {
