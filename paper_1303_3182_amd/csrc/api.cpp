@@ -145,8 +145,9 @@ std::shared_ptr<HostPlan> host_plan(const PlanKey &k) {
   if (!solve_kind(k.kind)) list = make_list(k.tree, k.p, k.q, k.param);
   hp->g = build_graph(list, spec);
   finalize(hp->g, k.priority != 0);
-  if (k.priority == TQR_PRIO_STATIC && use_static_order(k.nb, hp->g.tasks.size(), k.P))
-    static_list_order(hp->g, k.P, k.nb);
+  const bool zkind = (k.kind == PK_ZFACTOR || k.kind == PK_ZAPPLY);
+  if (k.priority == TQR_PRIO_STATIC && (zkind || use_static_order(k.nb, hp->g.tasks.size(), k.P)))
+    static_list_order(hp->g, k.P, k.nb, zkind);
   hp->valid = validate(hp->g);
   // the host structure is only needed for sequential order and statistics
   hp->g.preds.clear();
@@ -1625,9 +1626,15 @@ PlanKey zkey(int kind, int64_t m, int64_t n, int64_t nrhs, const ZResolved &z) {
   k.tree = z.tree;
   k.param = z.param;
   k.stripes = k.stripes_b = 1;
-  // the dynamic queue: the static order with the real kernels' costs was
-  // slower on the 8192 x 2048 complex QR (76.7 against 76.2 ms)
-  k.priority = TQR_PRIO_BOTTOM;
+  // nb 64: the static list order with the complex kernels' measured costs;
+  // nb 32 (no cost measurements): the dynamic queue
+  if (z.nb == 64) {
+    k.priority = TQR_PRIO_STATIC;
+    k.nb = z.nb;
+    k.P = device_cus() * zqr_occupancy(z.nb);
+  } else {
+    k.priority = TQR_PRIO_BOTTOM;
+  }
   return k;
 }
 

@@ -450,13 +450,28 @@ double gpu_cost_per_unit(int kind, int nb) {
     default: return 1.0;
   }
 }
+// The double-complex kernels at nb 64 (one reflector at a time on the
+// vector units, 512 threads per workgroup): microseconds per unit of
+// tab.kernels weight from a traced 8192 x 2048 factorization.
+double gpu_cost_per_unit_z(int kind) {
+  switch (kind) {
+    case K_GEQRT: return 26.3;
+    case K_TSQRT: return 23.3;
+    case K_TTQRT: return 49.6;
+    case K_UNMQR: return 6.1;
+    case K_TSMQR: return 3.5;
+    case K_TTMQR: return 6.6;
+    default: return 1.0;
+  }
+}
 }  // namespace
 
-double static_list_order(Graph &g, int P, int nb) {
+double static_list_order(Graph &g, int P, int nb, bool complex_kernels) {
   const int n = (int)g.tasks.size();
   P = std::max(P, 1);
   std::vector<double> w(n), bot(n, 0.0);
-  for (int t = 0; t < n; t++) w[t] = g.weight[t] * gpu_cost_per_unit(g.tasks[t].kind, nb);
+  for (int t = 0; t < n; t++)
+    w[t] = g.weight[t] * (complex_kernels ? gpu_cost_per_unit_z(g.tasks[t].kind) : gpu_cost_per_unit(g.tasks[t].kind, nb));
   for (int t = n - 1; t >= 0; t--) {  // list order is topological
     double m = 0.0;
     for (int e = g.succ_off[t]; e < g.succ_off[t + 1]; e++) m = std::max(m, bot[g.succ[e]]);

@@ -86,7 +86,7 @@ void finalize(Graph &g, bool priority);
 // ready0 to every task in simulated start order, with static_order.  Predecessors always start
 // before their successors in this order.  Returns the simulated makespan
 // (estimated microseconds).
-double static_list_order(Graph &g, int P, int nb);
+double static_list_order(Graph &g, int P, int nb, bool complex_kernels = false);
 
 // Task graph of the tile Cholesky inversion of t x t tiles (thesis chapter
 // "Cholesky Inversion", algorithm alg:InPlace: step 1 the tile Cholesky
