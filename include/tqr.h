@@ -358,8 +358,10 @@ int tqr_lstsq_noalloc(int64_t m, int64_t n, int64_t nrhs, const double *A, int64
  * beta = -sign(Re alpha) ||x||, tau = (beta - alpha) / beta,
  * v = [1; x2 / (alpha - beta)], H = I - tau v v^H, H^H x = beta e1 (tau = 0
  * when x2 = 0 and alpha is real).  Options from *o (NULL: defaults): nb 32
- * or 64 (default 64 when o is NULL), tree, param, kernels; ib, stripes and
- * the precision fields are ignored.  W: tqr_zworkspace_size(m, n, nrhs, o)
+ * or 64 (default 64 when o is NULL), tree, param, kernels; ib, stripes,
+ * priority and the precision fields are ignored (the ready order is the
+ * static list order at nb 64, the dynamic queue at nb 32).  W:
+ * tqr_zworkspace_size(m, n, nrhs, o)
  * bytes (nrhs: the widest B a later tqr_zapply_qh will take).  info: NULL
  * or a device int32 receiving 0 or TQR_INFO_TIMEOUT.  tqr_zapply_qh
  * overwrites B (m x nrhs, ldb >= m, complex) with Q^H B for a factorization
