@@ -256,21 +256,32 @@ __device__ __forceinline__ void zapply_regs(ZSmem<NB> &sm, cplx *C1g, cplx *C2g,
   // (exact, the masked terms add zeros).  Its unit entry is row r of C2
   // (MODE 0) or of C1, held by lane gr in slot kr; the slot loop is
   // unrolled, so that slot is a fixed register and only lane gr selects it.
+  // this lane's entries of the current reflector; the next one's are
+  // loaded while the current one is applied
+  cplx xv[NK];
+#pragma unroll
+  for (int k = 0; k < NK; k++) xv[k] = sm.X[g + G * k];
 #pragma unroll
   for (int kr = 0; kr < NK; kr++) {
     if (kr * G < nref) {
       const int gend = min(G, nref - kr * G);
       for (int gr = 0; gr < gend; gr++) {
         const int r = kr * G + gr;
+        const int rn = min(r + 1, NB - 1);  // (past the last reflector: loaded, unused)
+        cplx xn[NK];
+#pragma unroll
+        for (int k = 0; k < NK; k++) xn[k] = sm.X[rn * LD + g + G * k];
         cplx w{0.0, 0.0};
 #pragma unroll
-        for (int k = 0; k < NK; k++) w = cfma_conj(sm.X[r * LD + g + G * k], c2[k], w);
+        for (int k = 0; k < NK; k++) w = cfma_conj(xv[k], c2[k], w);
         const cplx id = (MODE == 0) ? c2[kr] : c1[kr];
         w = cadd(w, (g == gr) ? id : cplx{0.0, 0.0});
         w = group_sum_c<G>(w);
         const cplx f = cmul(conjc(sm.tau[r]), w);
 #pragma unroll
-        for (int k = 0; k < NK; k++) c2[k] = cfms(f, sm.X[r * LD + g + G * k], c2[k]);
+        for (int k = 0; k < NK; k++) c2[k] = cfms(f, xv[k], c2[k]);
+#pragma unroll
+        for (int k = 0; k < NK; k++) xv[k] = xn[k];
         if (MODE == 0)
           c2[kr] = (g == gr) ? csub(c2[kr], f) : c2[kr];
         else
